@@ -1,0 +1,168 @@
+/* qtp -- QTT-accelerated primal-dual interior-point Newton-step solver for
+ * frictional rigid-body contact, for one AMD MI355X (gfx950).
+ *
+ * C ABI.  All array arguments are DEVICE pointers unless a comment says
+ * "host".  The caller owns every pointer it passes; the library reads inputs
+ * during the call (or copies them into the context) and writes outputs into
+ * caller buffers.  Every launch goes on the stream given to qtp_create, and
+ * every call returns after its work is enqueued AND completed on that stream
+ * unless noted.  No call throws or aborts: errors are returned as a negative
+ * qtp_status and the message is available from qtp_last_error(ctx).
+ *
+ * Method: Corona, Gorsich, Jayakumar, Veerapaneni, "Tensor Train accelerated
+ * solvers for nonsmooth rigid body dynamics" (arXiv 1808.02558).  Each entry
+ * point names the passage that defines its operation.
+ *
+ * Layouts shared by several calls
+ * -------------------------------
+ * Unknowns.  A padded problem has n = 2^d unknowns.  Contact slot s in
+ * [0, S), S = floor(n/3), owns unknowns 3s + {0: normal, 1: t1, 2: t2}
+ * (Sec. 3.3: the contact hierarchy embedded in a uniform tree whose unused
+ * leaves are dummy unknowns with an identity block).  Unknowns 3S..n-1 are
+ * always dummies.
+ *
+ * BSR3 matrix.  A symmetric matrix on that layout stored as 3x3 blocks in
+ * block-compressed-row form over slots: row_ptr[S+1] (int32), col[nnzb]
+ * (int32 slot index, increasing within a block row), val[nnzb*9] (double,
+ * each block row-major).  A dummy slot's block row is one identity block.
+ * The dummy unknowns 3S..n-1 act as the identity and are not stored.
+ *
+ * QTT matrix (Sec. 3.2).  Ranks r_0..r_d (host int32 array of d+1 entries,
+ * r_0 = r_d = 1).  Core k (k = 1..d) is an array [r_{k-1}][2][2][r_k]
+ * indexed (alpha, i_k, j_k, beta), row-major; the cores are concatenated in
+ * order k = 1..d.  A(i, j) = G_1(i_1, j_1) ... G_d(i_d, j_d) with i_1 the
+ * most significant bit of the row index (Sec. 3.1 index convention).
+ */
+#ifndef QTP_H
+#define QTP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qtp_ctx_s* qtp_ctx;
+
+typedef enum {
+  QTP_OK = 0,
+  QTP_NOT_CONVERGED = 1, /* result written, but an iteration cap was hit */
+  QTP_E_ARG = -1,        /* invalid argument; nothing was launched */
+  QTP_E_OOM = -2,
+  QTP_E_HIP = -3,        /* a HIP runtime error; see qtp_last_error */
+  QTP_E_CAPACITY = -4,   /* contacts do not fit in floor(2^d/3) slots */
+  QTP_E_NUMERIC = -5,    /* NaN/Inf or a non-positive pivot */
+  QTP_E_STATE = -6       /* call order violated (e.g. solve before setup) */
+} qtp_status;
+
+typedef enum {
+  QTP_PREC_F64 = 0,  /* FP64 cores and intermediates */
+  QTP_PREC_F32 = 1,  /* FP32 cores and intermediates */
+  QTP_PREC_BF16 = 2  /* BF16 cores, FP32 accumulation and intermediates */
+} qtp_precision;
+
+typedef struct {
+  int precision;        /* qtp_precision of the QTT preconditioner apply */
+  double qtt_eps;       /* relative TT truncation tolerance (Algorithm 1) */
+  int qtt_rmax;         /* rank cap of the approximate inverse X */
+  int qtt_rmax_s;       /* rank cap of the compressed scaled matrix */
+  int ns_iters;         /* Newton-Schulz iterations for a cold inverse */
+  int ns_iters_hot;     /* Newton-Schulz iterations for a hot-started inverse */
+  int solve_mode;       /* 0: X * rhs + iterative refinement, 1: FGMRES */
+  double solve_tol;     /* relative residual of the Newton-step solve */
+  int fgmres_restart;   /* FGMRES restart length m */
+  int fgmres_maxit;     /* total FGMRES (or refinement) iteration cap */
+  double pdip_gap_tol;  /* PDIP stop: gap / m */
+  double pdip_dual_tol; /* PDIP stop: |r_dual|_inf in scaled units */
+  int pdip_maxit;
+  int warm_start;       /* 0 cold, 1 previous step, 2 learned */
+  uint64_t seed;
+} qtp_config;
+
+/* Fills a config with the defaults: FP64, eps 1e-2, rmax 32, rmax_s 16,
+ * FGMRES(30) to 1e-8, PDIP gap 1e-8 and dual 1e-4, 100 PDIP iterations. */
+void qtp_config_default(qtp_config* cfg);
+
+/* Creates a context bound to `hip_stream` (a hipStream_t; NULL = default
+ * stream) on the current device.  cfg may be NULL (defaults). */
+qtp_status qtp_create(const qtp_config* cfg, void* hip_stream, qtp_ctx* out);
+void qtp_destroy(qtp_ctx ctx);
+const char* qtp_last_error(qtp_ctx ctx);
+/* Updates the configuration of an existing context (host struct). */
+qtp_status qtp_set_config(qtp_ctx ctx, const qtp_config* cfg);
+
+/* ---------------------------------------------------------------------------
+ * Building blocks of the Newton-step solve (Sec. 3.2-3.3).
+ * ------------------------------------------------------------------------- */
+
+/* y = A x for a BSR3 matrix on n = 2^d unknowns (d = log2n): the sparse
+ * product with the Schur complement S_k, whose block pattern is that of
+ * N = D^T M^-1 D (Sec. 3.3, sparsity of N).  x, y: [n] double, must not
+ * alias.  Returns QTP_E_ARG for d outside [2, 30] or null pointers. */
+qtp_status qtp_bsr_spmv(qtp_ctx ctx, int log2n, const int32_t* row_ptr,
+                        const int32_t* col, const double* val, const double* x,
+                        double* y);
+
+/* y = A x for a QTT matrix (Sec. 3.2: the TT matrix-vector product contracts
+ * one dimension at a time, O(r^2 N log N)).  ranks: host [d+1].  cores:
+ * device, element type by `precision` (double / float / bf16 as uint16).
+ * x, y: [2^d] double, may not alias.  Intermediates use the context's
+ * workspace.  Ranks must be in [1, 256]. */
+qtp_status qtp_qtt_apply(qtp_ctx ctx, int d, const int32_t* ranks,
+                         const void* cores, int precision, const double* x,
+                         double* y);
+
+/* ---------------------------------------------------------------------------
+ * The Newton-step solve on a loaded matrix (Sec. 3.3, "TT Newton system
+ * solver": the approximate TT inverse used as a direct solver with iterative
+ * refinement, or as the preconditioner of a Krylov method).
+ * ------------------------------------------------------------------------- */
+
+/* Copies a BSR3 Newton matrix S into the context (device to device).
+ * nnzb = row_ptr[S] is read back from the device. */
+qtp_status qtp_set_newton_matrix(qtp_ctx ctx, int log2n, const int32_t* row_ptr,
+                                 const int32_t* col, const double* val);
+
+/* Builds the preconditioner for the loaded matrix: the block-Jacobi factors
+ * L = blockdiag(chol S_ss), the QTT compression of L^-1 S L^-T (a right-to-
+ * left block-sparse Algorithm 1) and its approximate inverse X (Newton-
+ * Schulz with TT rounding).  hot != 0 starts Newton-Schulz from the previous
+ * X (the inverse update of Sec. 3.2-3.3); otherwise from a scaled identity.
+ * Preconditioner P = L^-T X L^-1.  Must follow qtp_set_newton_matrix. */
+qtp_status qtp_precond_build(qtp_ctx ctx, int hot);
+
+/* Same as qtp_precond_build but loads a given FP64 QTT inverse X instead of
+ * computing one (the block-Jacobi factors are still computed from S). */
+qtp_status qtp_precond_load_qtt(qtp_ctx ctx, int d, const int32_t* ranks,
+                                const double* cores);
+
+typedef struct {
+  int iterations;        /* FGMRES iterations or refinement steps */
+  double rel_residual;   /* |b - S x| / |b| recomputed at the end */
+  double ms;             /* wall time of the solve on the stream */
+} qtp_solve_stats;
+
+/* Solves S x = rhs to the configured relative residual.  rhs, x: [2^d]
+ * double (may not alias).  Returns QTP_NOT_CONVERGED (with x and stats
+ * written) when the iteration cap is reached. */
+qtp_status qtp_newton_solve(qtp_ctx ctx, const double* rhs, double* x,
+                            qtp_solve_stats* stats);
+
+/* Applies the current preconditioner: z = L^-T X L^-1 v. */
+qtp_status qtp_precond_apply(qtp_ctx ctx, const double* v, double* z);
+
+/* Ranks of the current compressed matrix (which = 0) or inverse (which = 1):
+ * writes up to d+1 ints into ranks_host and returns d, or a negative status. */
+int qtp_get_qtt_ranks(qtp_ctx ctx, int which, int32_t* ranks_host);
+
+/* Copies the FP64 cores of the compressed matrix (which = 0) or inverse
+ * (which = 1) into a device buffer of at least `capacity` doubles. */
+qtp_status qtp_get_qtt_cores(qtp_ctx ctx, int which, double* cores,
+                             int64_t capacity);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QTP_H */

@@ -1,0 +1,198 @@
+"""ctypes binding of libqtp.so (argument marshalling only).
+
+Each method of :class:`Context` calls the C function of the same name in
+``include/qtp.h``.  Tensors must be CUDA (HIP) tensors of the documented
+dtype; their device pointers and the current stream are passed as is.
+Nothing here computes any part of the method.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqtp.so")
+
+QTP_OK = 0
+QTP_NOT_CONVERGED = 1
+STATUS = {0: "QTP_OK", 1: "QTP_NOT_CONVERGED", -1: "QTP_E_ARG", -2: "QTP_E_OOM",
+          -3: "QTP_E_HIP", -4: "QTP_E_CAPACITY", -5: "QTP_E_NUMERIC",
+          -6: "QTP_E_STATE"}
+PREC = {"f64": 0, "f32": 1, "bf16": 2}
+
+
+class QtpError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("precision", ctypes.c_int),
+        ("qtt_eps", ctypes.c_double),
+        ("qtt_rmax", ctypes.c_int),
+        ("qtt_rmax_s", ctypes.c_int),
+        ("ns_iters", ctypes.c_int),
+        ("ns_iters_hot", ctypes.c_int),
+        ("solve_mode", ctypes.c_int),
+        ("solve_tol", ctypes.c_double),
+        ("fgmres_restart", ctypes.c_int),
+        ("fgmres_maxit", ctypes.c_int),
+        ("pdip_gap_tol", ctypes.c_double),
+        ("pdip_dual_tol", ctypes.c_double),
+        ("pdip_maxit", ctypes.c_int),
+        ("warm_start", ctypes.c_int),
+        ("seed", ctypes.c_uint64),
+    ]
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("rel_residual", ctypes.c_double),
+                ("ms", ctypes.c_double)]
+
+
+_lib = None
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_I64 = ctypes.c_int64
+SIGNATURES = {
+    "qtp_config_default": (None, [_P]),
+    "qtp_create": (_I, [_P, _P, _P]),
+    "qtp_destroy": (None, [_P]),
+    "qtp_last_error": (ctypes.c_char_p, [_P]),
+    "qtp_set_config": (_I, [_P, _P]),
+    "qtp_bsr_spmv": (_I, [_P, _I, _P, _P, _P, _P, _P]),
+    "qtp_qtt_apply": (_I, [_P, _I, _P, _P, _I, _P, _P]),
+    "qtp_set_newton_matrix": (_I, [_P, _I, _P, _P, _P]),
+    "qtp_precond_build": (_I, [_P, _I]),
+    "qtp_precond_load_qtt": (_I, [_P, _I, _P, _P]),
+    "qtp_newton_solve": (_I, [_P, _P, _P, _P]),
+    "qtp_precond_apply": (_I, [_P, _P, _P]),
+    "qtp_get_qtt_ranks": (_I, [_P, _I, _P]),
+    "qtp_get_qtt_cores": (_I, [_P, _I, _P, _I64]),
+}
+
+
+def load(path=LIB_PATH):
+    """Load libqtp.so; raises if it is missing (no fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built: run python -m "
+                          "paper_1808_02558_amd.build")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def default_config(**kw):
+    lib = load()
+    c = Config()
+    lib.qtp_config_default(ctypes.byref(c))
+    for k, v in kw.items():
+        if k == "precision" and isinstance(v, str):
+            v = PREC[v]
+        setattr(c, k, v)
+    return c
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _ranks(ranks):
+    arr = (ctypes.c_int32 * len(ranks))(*[int(r) for r in ranks])
+    return arr
+
+
+class Context:
+    """One qtp_ctx bound to the current torch HIP stream."""
+
+    def __init__(self, cfg=None, stream=None, **kw):
+        import torch
+        self.lib = load()
+        self.cfg = cfg if cfg is not None else default_config(**kw)
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self.stream = stream
+        h = ctypes.c_void_p()
+        st = self.lib.qtp_create(ctypes.byref(self.cfg), ctypes.c_void_p(stream),
+                                 ctypes.byref(h))
+        if st != QTP_OK:
+            raise QtpError(st, self.lib.qtp_last_error(None).decode())
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.qtp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st, allow_nc=False):
+        if st == QTP_OK or (allow_nc and st == QTP_NOT_CONVERGED):
+            return st
+        raise QtpError(st, self.lib.qtp_last_error(self.h).decode())
+
+    def qtp_set_config(self, **kw):
+        for k, v in kw.items():
+            if k == "precision" and isinstance(v, str):
+                v = PREC[v]
+            setattr(self.cfg, k, v)
+        return self._check(self.lib.qtp_set_config(self.h, ctypes.byref(self.cfg)))
+
+    def qtp_bsr_spmv(self, log2n, row_ptr, col, val, x, y):
+        return self._check(self.lib.qtp_bsr_spmv(
+            self.h, log2n, _ptr(row_ptr), _ptr(col), _ptr(val), _ptr(x), _ptr(y)))
+
+    def qtp_qtt_apply(self, d, ranks, cores, precision, x, y):
+        prec = PREC[precision] if isinstance(precision, str) else precision
+        return self._check(self.lib.qtp_qtt_apply(
+            self.h, d, _ranks(ranks), _ptr(cores), prec, _ptr(x), _ptr(y)))
+
+    def qtp_set_newton_matrix(self, log2n, row_ptr, col, val):
+        return self._check(self.lib.qtp_set_newton_matrix(
+            self.h, log2n, _ptr(row_ptr), _ptr(col), _ptr(val)))
+
+    def qtp_precond_build(self, hot=0):
+        return self._check(self.lib.qtp_precond_build(self.h, int(hot)))
+
+    def qtp_precond_load_qtt(self, d, ranks, cores):
+        return self._check(self.lib.qtp_precond_load_qtt(
+            self.h, d, _ranks(ranks), _ptr(cores)))
+
+    def qtp_newton_solve(self, rhs, x):
+        st = SolveStats()
+        rc = self._check(self.lib.qtp_newton_solve(
+            self.h, _ptr(rhs), _ptr(x), ctypes.byref(st)), allow_nc=True)
+        return rc, st
+
+    def qtp_precond_apply(self, v, z):
+        return self._check(self.lib.qtp_precond_apply(self.h, _ptr(v), _ptr(z)))
+
+    def qtp_get_qtt_ranks(self, which):
+        buf = (ctypes.c_int32 * 64)()
+        d = self.lib.qtp_get_qtt_ranks(self.h, which, buf)
+        if d < 0:
+            raise QtpError(d, "no QTT available")
+        return [int(buf[k]) for k in range(d + 1)]
+
+    def qtp_get_qtt_cores(self, which):
+        import torch
+        ranks = self.qtp_get_qtt_ranks(which)
+        tot = sum(ranks[k] * 4 * ranks[k + 1] for k in range(len(ranks) - 1))
+        out = torch.empty(tot, dtype=torch.float64, device="cuda")
+        self._check(self.lib.qtp_get_qtt_cores(self.h, which, _ptr(out), tot))
+        return ranks, out

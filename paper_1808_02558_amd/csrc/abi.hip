@@ -1,0 +1,275 @@
+// C-ABI of the qtp library: argument checks, context management, and the
+// translation of internal errors into qtp_status codes.  Nothing here
+// computes; every step runs in the kernels of the other files.
+#include <cstring>
+
+#include "context.h"
+
+using qtp::Ctx;
+using qtp::Error;
+
+struct qtp_ctx_s {
+  Ctx c;
+};
+
+namespace {
+
+thread_local std::string g_create_error;
+
+template <class F>
+qtp_status guarded(qtp_ctx ctx, F&& f) {
+  if (!ctx) return QTP_E_ARG;
+  try {
+    ctx->c.err.clear();
+    return (qtp_status)f(ctx->c);
+  } catch (const Error& e) {
+    ctx->c.err = e.what();
+    return (qtp_status)e.status;
+  } catch (const std::bad_alloc&) {
+    ctx->c.err = "host allocation failed";
+    return QTP_E_OOM;
+  } catch (const std::exception& e) {
+    ctx->c.err = e.what();
+    return QTP_E_HIP;
+  }
+}
+
+bool valid_d(int d) { return d >= 2 && d <= 30; }
+
+}  // namespace
+
+int64_t qtp::Qtt::total() const {
+  int64_t t = 0;
+  for (int k = 0; k < d; ++k) t += (int64_t)ranks[k] * 4 * ranks[k + 1];
+  return t;
+}
+
+void qtp::Ctx::check_cfg() {
+  QTP_REQUIRE(cfg.precision >= 0 && cfg.precision <= 2, QTP_E_ARG, "bad precision");
+  QTP_REQUIRE(cfg.qtt_rmax >= 1 && cfg.qtt_rmax <= 256, QTP_E_ARG, "qtt_rmax out of [1,256]");
+  QTP_REQUIRE(cfg.qtt_rmax_s >= 1 && cfg.qtt_rmax_s <= 64, QTP_E_ARG, "qtt_rmax_s out of [1,64]");
+  QTP_REQUIRE(cfg.qtt_eps > 0.0 && cfg.qtt_eps < 1.0, QTP_E_ARG, "qtt_eps out of (0,1)");
+  QTP_REQUIRE(cfg.fgmres_restart >= 1 && cfg.fgmres_restart <= 63, QTP_E_ARG,
+              "fgmres_restart out of [1,63]");
+  QTP_REQUIRE(cfg.fgmres_maxit >= 1, QTP_E_ARG, "fgmres_maxit < 1");
+  QTP_REQUIRE(cfg.solve_tol > 0.0, QTP_E_ARG, "solve_tol <= 0");
+  QTP_REQUIRE(cfg.solve_mode == 0 || cfg.solve_mode == 1, QTP_E_ARG, "bad solve_mode");
+  QTP_REQUIRE(cfg.ns_iters >= 0 && cfg.ns_iters_hot >= 0, QTP_E_ARG, "ns_iters < 0");
+}
+
+extern "C" {
+
+void qtp_config_default(qtp_config* cfg) {
+  if (!cfg) return;
+  std::memset(cfg, 0, sizeof(*cfg));
+  cfg->precision = QTP_PREC_F64;
+  cfg->qtt_eps = 1e-2;
+  cfg->qtt_rmax = 32;
+  cfg->qtt_rmax_s = 16;
+  cfg->ns_iters = 8;
+  cfg->ns_iters_hot = 2;
+  cfg->solve_mode = 1;
+  cfg->solve_tol = 1e-8;
+  cfg->fgmres_restart = 30;
+  cfg->fgmres_maxit = 1000;
+  cfg->pdip_gap_tol = 1e-8;
+  cfg->pdip_dual_tol = 1e-4;
+  cfg->pdip_maxit = 100;
+  cfg->warm_start = 0;
+  cfg->seed = 0;
+}
+
+qtp_status qtp_create(const qtp_config* cfg, void* hip_stream, qtp_ctx* out) {
+  if (!out) return QTP_E_ARG;
+  *out = nullptr;
+  qtp_ctx h = nullptr;
+  try {
+    h = new qtp_ctx_s();
+  } catch (...) {
+    return QTP_E_OOM;
+  }
+  if (cfg) h->c.cfg = *cfg;
+  else qtp_config_default(&h->c.cfg);
+  h->c.stream = static_cast<hipStream_t>(hip_stream);
+  qtp_status st = guarded(h, [](Ctx& c) {
+    c.check_cfg();
+    return QTP_OK;
+  });
+  if (st != QTP_OK) {
+    g_create_error = h->c.err;
+    delete h;
+    return st;
+  }
+  *out = h;
+  return QTP_OK;
+}
+
+void qtp_destroy(qtp_ctx ctx) {
+  if (!ctx) return;
+  if (ctx->c.stream) (void)hipStreamSynchronize(ctx->c.stream);
+  else (void)hipDeviceSynchronize();
+  delete ctx;
+}
+
+const char* qtp_last_error(qtp_ctx ctx) {
+  if (!ctx) return g_create_error.c_str();
+  return ctx->c.err.c_str();
+}
+
+qtp_status qtp_set_config(qtp_ctx ctx, const qtp_config* cfg) {
+  if (!cfg) return QTP_E_ARG;
+  return guarded(ctx, [&](Ctx& c) {
+    qtp_config old = c.cfg;
+    c.cfg = *cfg;
+    try {
+      c.check_cfg();
+    } catch (...) {
+      c.cfg = old;
+      throw;
+    }
+    c.X.lp_prec = 0;  // reduced-precision copies follow the new precision
+    return QTP_OK;
+  });
+}
+
+qtp_status qtp_bsr_spmv(qtp_ctx ctx, int log2n, const int32_t* row_ptr,
+                        const int32_t* col, const double* val, const double* x,
+                        double* y) {
+  return guarded(ctx, [&](Ctx& c) {
+    QTP_REQUIRE(valid_d(log2n), QTP_E_ARG, "log2n out of [2,30]");
+    QTP_REQUIRE(row_ptr && col && val && x && y, QTP_E_ARG, "null pointer");
+    QTP_REQUIRE(x != y, QTP_E_ARG, "x and y alias");
+    const int64_t n = (int64_t)1 << log2n;
+    qtp::bsr_spmv(c.stream, (int)(n / 3), n, row_ptr, col, val, x, y);
+    QTP_HIP(hipStreamSynchronize(c.stream));
+    return QTP_OK;
+  });
+}
+
+qtp_status qtp_qtt_apply(qtp_ctx ctx, int d, const int32_t* ranks,
+                         const void* cores, int precision, const double* x,
+                         double* y) {
+  return guarded(ctx, [&](Ctx& c) {
+    QTP_REQUIRE(d >= 1 && d <= 30, QTP_E_ARG, "d out of [1,30]");
+    QTP_REQUIRE(ranks && cores && x && y, QTP_E_ARG, "null pointer");
+    QTP_REQUIRE(x != y, QTP_E_ARG, "x and y alias");
+    QTP_REQUIRE(precision >= 0 && precision <= 2, QTP_E_ARG, "bad precision");
+    QTP_REQUIRE(ranks[0] == 1 && ranks[d] == 1, QTP_E_ARG, "r_0 and r_d must be 1");
+    for (int k = 0; k <= d; ++k)
+      QTP_REQUIRE(ranks[k] >= 1 && ranks[k] <= 256, QTP_E_ARG, "rank out of [1,256]");
+    c.qtt_work.ensure(qtp::qtt_apply_workspace(d, ranks, precision));
+    qtp::qtt_apply(c.stream, d, ranks, cores, precision, x, y, c.qtt_work.get());
+    QTP_HIP(hipStreamSynchronize(c.stream));
+    return QTP_OK;
+  });
+}
+
+qtp_status qtp_set_newton_matrix(qtp_ctx ctx, int log2n, const int32_t* row_ptr,
+                                 const int32_t* col, const double* val) {
+  return guarded(ctx, [&](Ctx& c) {
+    QTP_REQUIRE(valid_d(log2n), QTP_E_ARG, "log2n out of [2,30]");
+    QTP_REQUIRE(row_ptr && col && val, QTP_E_ARG, "null pointer");
+    const int64_t n = (int64_t)1 << log2n;
+    const int ns = (int)(n / 3);
+    int32_t h_nnzb = 0;
+    QTP_HIP(hipMemcpyAsync(&h_nnzb, row_ptr + ns, sizeof(int32_t),
+                           hipMemcpyDeviceToHost, c.stream));
+    QTP_HIP(hipStreamSynchronize(c.stream));
+    QTP_REQUIRE(h_nnzb >= ns, QTP_E_ARG, "row_ptr[S] smaller than the slot count");
+    c.log2n = log2n;
+    c.n = n;
+    c.nslots = ns;
+    c.nnzb = h_nnzb;
+    c.rp.ensure(sizeof(int32_t) * (ns + 1));
+    c.col.ensure(sizeof(int32_t) * (size_t)h_nnzb);
+    c.val.ensure(sizeof(double) * 9 * (size_t)h_nnzb);
+    QTP_HIP(hipMemcpyAsync(c.rp.get(), row_ptr, sizeof(int32_t) * (ns + 1),
+                           hipMemcpyDeviceToDevice, c.stream));
+    QTP_HIP(hipMemcpyAsync(c.col.get(), col, sizeof(int32_t) * (size_t)h_nnzb,
+                           hipMemcpyDeviceToDevice, c.stream));
+    QTP_HIP(hipMemcpyAsync(c.val.get(), val, sizeof(double) * 9 * (size_t)h_nnzb,
+                           hipMemcpyDeviceToDevice, c.stream));
+    QTP_HIP(hipStreamSynchronize(c.stream));
+    c.have_matrix = true;
+    c.have_precond = false;
+    return QTP_OK;
+  });
+}
+
+qtp_status qtp_precond_build(qtp_ctx ctx, int hot) {
+  return guarded(ctx, [&](Ctx& c) {
+    qtp::precond_factor(c);
+    c.have_precond = true;
+    qtp::build_inverse(c, hot);
+    QTP_HIP(hipStreamSynchronize(c.stream));
+    return QTP_OK;
+  });
+}
+
+qtp_status qtp_precond_load_qtt(qtp_ctx ctx, int d, const int32_t* ranks,
+                                const double* cores) {
+  return guarded(ctx, [&](Ctx& c) {
+    QTP_REQUIRE(c.have_matrix, QTP_E_STATE, "no Newton matrix loaded");
+    QTP_REQUIRE(d == c.log2n, QTP_E_ARG, "QTT size does not match the matrix");
+    QTP_REQUIRE(ranks && cores, QTP_E_ARG, "null pointer");
+    QTP_REQUIRE(ranks[0] == 1 && ranks[d] == 1, QTP_E_ARG, "r_0 and r_d must be 1");
+    for (int k = 0; k <= d; ++k)
+      QTP_REQUIRE(ranks[k] >= 1 && ranks[k] <= 256, QTP_E_ARG, "rank out of [1,256]");
+    qtp::precond_factor(c);
+    c.have_precond = true;
+    c.X.d = d;
+    c.X.ranks.assign(ranks, ranks + d + 1);
+    const int64_t tot = c.X.total();
+    c.X.cores.ensure(sizeof(double) * tot);
+    QTP_HIP(hipMemcpyAsync(c.X.cores.get(), cores, sizeof(double) * tot,
+                           hipMemcpyDeviceToDevice, c.stream));
+    c.X.lp_prec = 0;
+    c.have_inverse = true;
+    QTP_HIP(hipStreamSynchronize(c.stream));
+    return QTP_OK;
+  });
+}
+
+qtp_status qtp_newton_solve(qtp_ctx ctx, const double* rhs, double* x,
+                            qtp_solve_stats* stats) {
+  return guarded(ctx, [&](Ctx& c) {
+    QTP_REQUIRE(rhs && x, QTP_E_ARG, "null pointer");
+    QTP_REQUIRE(rhs != x, QTP_E_ARG, "rhs and x alias");
+    qtp_solve_stats local{};
+    qtp_solve_stats* st = stats ? stats : &local;
+    return qtp::newton_solve(c, rhs, x, st);
+  });
+}
+
+qtp_status qtp_precond_apply(qtp_ctx ctx, const double* v, double* z) {
+  return guarded(ctx, [&](Ctx& c) {
+    QTP_REQUIRE(v && z && v != z, QTP_E_ARG, "bad vector pointers");
+    qtp::precond_apply(c, v, z);
+    QTP_HIP(hipStreamSynchronize(c.stream));
+    return QTP_OK;
+  });
+}
+
+int qtp_get_qtt_ranks(qtp_ctx ctx, int which, int32_t* ranks_host) {
+  if (!ctx || !ranks_host || (which != 0 && which != 1)) return QTP_E_ARG;
+  const qtp::Qtt& q = which == 0 ? ctx->c.A : ctx->c.X;
+  if (q.d == 0) return QTP_E_STATE;
+  for (int k = 0; k <= q.d; ++k) ranks_host[k] = q.ranks[k];
+  return q.d;
+}
+
+qtp_status qtp_get_qtt_cores(qtp_ctx ctx, int which, double* cores,
+                             int64_t capacity) {
+  return guarded(ctx, [&](Ctx& c) {
+    QTP_REQUIRE(cores && (which == 0 || which == 1), QTP_E_ARG, "bad arguments");
+    const qtp::Qtt& q = which == 0 ? c.A : c.X;
+    QTP_REQUIRE(q.d > 0, QTP_E_STATE, "no QTT of that kind");
+    QTP_REQUIRE(capacity >= q.total(), QTP_E_ARG, "capacity too small");
+    QTP_HIP(hipMemcpyAsync(cores, q.cores.get(), sizeof(double) * q.total(),
+                           hipMemcpyDeviceToDevice, c.stream));
+    QTP_HIP(hipStreamSynchronize(c.stream));
+    return QTP_OK;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,351 @@
+// Vector kernels of the Krylov solve and the block-Jacobi scaling.
+//
+// Reductions are deterministic: every block writes one partial sum per
+// output in a fixed order, and a second single-block pass adds the partials
+// in index order.  No floating-point atomics.
+#include "ops.h"
+
+namespace qtp {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kMaxBlocks = 1024;
+constexpr int kMaxVec = 64;  // most vectors a multi-dot handles per pass
+
+__device__ inline double block_sum(double v, double* sh) {
+  // wavefront reduction, then across the 4 wavefronts of the block
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < kThreads / 64; ++i) s += sh[i];
+  }
+  return s;  // valid in thread 0
+}
+
+// partial[blk * nvec + l] = sum over this block's chunk of V_l[i] * w[i]
+__global__ __launch_bounds__(kThreads) void multi_dot_kernel(
+    int nvec, const double* __restrict__ V, int64_t ldv,
+    const double* __restrict__ w, int64_t n, double* __restrict__ partial) {
+  __shared__ double sh[kThreads / 64];
+  const int64_t stride = (int64_t)gridDim.x * kThreads;
+  for (int l = 0; l < nvec; ++l) {
+    double acc = 0.0;
+    const double* v = V + (int64_t)l * ldv;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+         i += stride)
+      acc += v[i] * w[i];
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * nvec + l] = s;
+  }
+}
+
+// w -= sum_l h_l V_l (in place), then partial dots of V_l with the new w
+// (mode 0) or the partial of |w|^2 (mode 1).
+template <int MODE>
+__global__ __launch_bounds__(kThreads) void cgs_update_kernel(
+    int nvec, const double* __restrict__ V, int64_t ldv,
+    const double* __restrict__ h, double* __restrict__ w, int64_t n,
+    double* __restrict__ partial) {
+  __shared__ double sh[kThreads / 64];
+  __shared__ double hs[kMaxVec];
+  if (threadIdx.x < nvec) hs[threadIdx.x] = h[threadIdx.x];
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * kThreads;
+  double acc[MODE == 0 ? kMaxVec : 1];
+  if (MODE == 0) {
+    for (int l = 0; l < nvec; ++l) acc[l] = 0.0;
+  } else {
+    acc[0] = 0.0;
+  }
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+       i += stride) {
+    double wi = w[i];
+    for (int l = 0; l < nvec; ++l) wi -= hs[l] * V[(int64_t)l * ldv + i];
+    w[i] = wi;
+    if (MODE == 0) {
+      for (int l = 0; l < nvec; ++l) acc[l] += V[(int64_t)l * ldv + i] * wi;
+    } else {
+      acc[0] += wi * wi;
+    }
+  }
+  const int nout = MODE == 0 ? nvec : 1;
+  for (int l = 0; l < nout; ++l) {
+    const double s = block_sum(acc[l], sh);
+    if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * nout + l] = s;
+  }
+}
+
+// out[l] = sum_b partial[b * nvec + l], fixed order
+__global__ void finish_kernel(int nblk, int nvec, const double* __restrict__ partial,
+                              double* __restrict__ out) {
+  __shared__ double sh[kThreads / 64];
+  for (int l = 0; l < nvec; ++l) {
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kThreads)
+      acc += partial[(int64_t)b * nvec + l];
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) out[l] = s;
+  }
+}
+
+__global__ void scale_kernel(const double* __restrict__ a, int inv,
+                             const double* __restrict__ x, double* __restrict__ y,
+                             int64_t n) {
+  const double s = inv ? 1.0 / a[0] : a[0];
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads)
+    y[i] = s * x[i];
+}
+
+__global__ void multi_axpy_kernel(int nvec, const double* __restrict__ X,
+                                  int64_t ldx, const double* __restrict__ c,
+                                  double* __restrict__ y, int64_t n) {
+  __shared__ double cs[kMaxVec];
+  if (threadIdx.x < nvec) cs[threadIdx.x] = c[threadIdx.x];
+  __syncthreads();
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads) {
+    double v = y[i];
+    for (int l = 0; l < nvec; ++l) v += cs[l] * X[(int64_t)l * ldx + i];
+    y[i] = v;
+  }
+}
+
+__global__ void sub_kernel(const double* __restrict__ x, const double* __restrict__ y,
+                           double* __restrict__ z, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads)
+    z[i] = x[i] - y[i];
+}
+
+__global__ void add_kernel(const double* __restrict__ x, double* __restrict__ y,
+                           int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads)
+    y[i] += x[i];
+}
+
+__global__ void nonfinite_kernel(const double* __restrict__ x, int64_t n,
+                                 int* __restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads)
+    if (!isfinite(x[i])) out[0] = 1;  // benign race: every writer stores 1
+}
+
+// ---- block Jacobi -----------------------------------------------------------
+
+__global__ void bj_factor_kernel(int nslots, const int32_t* __restrict__ rp,
+                                 const int32_t* __restrict__ col,
+                                 const double* __restrict__ val,
+                                 double* __restrict__ Linv, int* __restrict__ bad) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nslots) return;
+  int b = -1;
+  for (int q = rp[s]; q < rp[s + 1]; ++q)
+    if (col[q] == s) { b = q; break; }
+  double out[6] = {1, 0, 1, 0, 0, 1};
+  if (b < 0) {
+    bad[0] = 1;
+  } else {
+    const double* A = val + (int64_t)b * 9;
+    // Cholesky A = L L^T of the symmetric part (lower triangle read)
+    const double a00 = A[0], a10 = A[3], a11 = A[4], a20 = A[6], a21 = A[7],
+                 a22 = A[8];
+    if (!(a00 > 0.0)) {
+      bad[0] = 1;
+    } else {
+      const double l00 = sqrt(a00);
+      const double l10 = a10 / l00;
+      const double l20 = a20 / l00;
+      const double d1 = a11 - l10 * l10;
+      if (!(d1 > 0.0)) {
+        bad[0] = 1;
+      } else {
+        const double l11 = sqrt(d1);
+        const double l21 = (a21 - l20 * l10) / l11;
+        const double d2 = a22 - l20 * l20 - l21 * l21;
+        if (!(d2 > 0.0)) {
+          bad[0] = 1;
+        } else {
+          const double l22 = sqrt(d2);
+          // inverse of the lower-triangular L
+          const double m00 = 1.0 / l00;
+          const double m11 = 1.0 / l11;
+          const double m22 = 1.0 / l22;
+          const double m10 = -l10 * m00 / l11;
+          const double m21 = -l21 * m11 / l22;
+          const double m20 = -(l20 * m00 + l21 * m10) / l22;
+          out[0] = m00; out[1] = m10; out[2] = m11;
+          out[3] = m20; out[4] = m21; out[5] = m22;
+        }
+      }
+    }
+  }
+  for (int q = 0; q < 6; ++q) Linv[(int64_t)s * 6 + q] = out[q];
+}
+
+__global__ void bj_apply_kernel(int nslots, int64_t n, const double* __restrict__ Linv,
+                                int trans, const double* __restrict__ x,
+                                double* __restrict__ y) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < nslots) {
+    const double* m = Linv + s * 6;
+    const double x0 = x[3 * s], x1 = x[3 * s + 1], x2 = x[3 * s + 2];
+    double y0, y1, y2;
+    if (!trans) {
+      y0 = m[0] * x0;
+      y1 = m[1] * x0 + m[2] * x1;
+      y2 = m[3] * x0 + m[4] * x1 + m[5] * x2;
+    } else {
+      y0 = m[0] * x0 + m[1] * x1 + m[3] * x2;
+      y1 = m[2] * x1 + m[4] * x2;
+      y2 = m[5] * x2;
+    }
+    y[3 * s] = y0;
+    y[3 * s + 1] = y1;
+    y[3 * s + 2] = y2;
+  } else {
+    const int64_t u = 3 * (int64_t)nslots + (s - nslots);
+    if (u < n) y[u] = x[u];
+  }
+}
+
+// vout_b = L_s^-1 A_b L_c^-T for every block b = (s, c)
+__global__ void bj_scale_matrix_kernel(int nslots, const int32_t* __restrict__ rp,
+                                       const int32_t* __restrict__ col,
+                                       const double* __restrict__ val,
+                                       const double* __restrict__ Linv,
+                                       double* __restrict__ vout) {
+  const int s = blockIdx.x;
+  double Ls[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  const double* m = Linv + (int64_t)s * 6;
+  Ls[0] = m[0]; Ls[3] = m[1]; Ls[4] = m[2]; Ls[6] = m[3]; Ls[7] = m[4]; Ls[8] = m[5];
+  for (int q = rp[s] + threadIdx.x; q < rp[s + 1]; q += blockDim.x) {
+    const int c = col[q];
+    const double* mc = Linv + (int64_t)c * 6;
+    double Lc[9] = {mc[0], 0, 0, mc[1], mc[2], 0, mc[3], mc[4], mc[5]};
+    const double* A = val + (int64_t)q * 9;
+    double T[9];
+    for (int r = 0; r < 3; ++r)
+      for (int cc = 0; cc < 3; ++cc) {
+        double acc = 0.0;
+        for (int t = 0; t < 3; ++t) acc += Ls[3 * r + t] * A[3 * t + cc];
+        T[3 * r + cc] = acc;
+      }
+    double* O = vout + (int64_t)q * 9;
+    for (int r = 0; r < 3; ++r)
+      for (int cc = 0; cc < 3; ++cc) {
+        double acc = 0.0;
+        for (int t = 0; t < 3; ++t) acc += T[3 * r + t] * Lc[3 * cc + t];
+        O[3 * r + cc] = acc;
+      }
+  }
+}
+
+int grid_for(int64_t n) {
+  int64_t b = (n + kThreads - 1) / kThreads;
+  if (b > kMaxBlocks) b = kMaxBlocks;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+}  // namespace
+
+int reduce_blocks(int64_t n) { return grid_for(n); }
+
+void multi_dot(hipStream_t s, int nvec, const double* V, int64_t ldv,
+               const double* w, int64_t n, double* partial, double* out) {
+  QTP_REQUIRE(nvec >= 1 && nvec <= kMaxVec, -1, "multi_dot: nvec out of range");
+  const int nb = grid_for(n);
+  multi_dot_kernel<<<nb, kThreads, 0, s>>>(nvec, V, ldv, w, n, partial);
+  QTP_CHECK_LAUNCH();
+  finish_kernel<<<1, kThreads, 0, s>>>(nb, nvec, partial, out);
+  QTP_CHECK_LAUNCH();
+}
+
+void cgs_update_dot(hipStream_t s, int nvec, const double* V, int64_t ldv,
+                    const double* h, double* w, int64_t n, double* partial,
+                    double* out) {
+  QTP_REQUIRE(nvec >= 1 && nvec <= kMaxVec, -1, "cgs_update_dot: nvec out of range");
+  const int nb = grid_for(n);
+  cgs_update_kernel<0><<<nb, kThreads, 0, s>>>(nvec, V, ldv, h, w, n, partial);
+  QTP_CHECK_LAUNCH();
+  finish_kernel<<<1, kThreads, 0, s>>>(nb, nvec, partial, out);
+  QTP_CHECK_LAUNCH();
+}
+
+void cgs_update_norm2(hipStream_t s, int nvec, const double* V, int64_t ldv,
+                      const double* h, double* w, int64_t n, double* partial,
+                      double* out) {
+  QTP_REQUIRE(nvec >= 1 && nvec <= kMaxVec, -1, "cgs_update_norm2: nvec out of range");
+  const int nb = grid_for(n);
+  cgs_update_kernel<1><<<nb, kThreads, 0, s>>>(nvec, V, ldv, h, w, n, partial);
+  QTP_CHECK_LAUNCH();
+  finish_kernel<<<1, kThreads, 0, s>>>(nb, 1, partial, out);
+  QTP_CHECK_LAUNCH();
+}
+
+void dot(hipStream_t s, const double* x, const double* y, int64_t n,
+         double* partial, double* out) {
+  multi_dot(s, 1, x, n, y, n, partial, out);
+}
+
+void scale_dev(hipStream_t s, const double* a_dev, int inv, const double* x,
+               double* y, int64_t n) {
+  scale_kernel<<<grid_for(n), kThreads, 0, s>>>(a_dev, inv, x, y, n);
+  QTP_CHECK_LAUNCH();
+}
+
+void multi_axpy(hipStream_t s, int nvec, const double* X, int64_t ldx,
+                const double* c, double* y, int64_t n) {
+  QTP_REQUIRE(nvec >= 1 && nvec <= kMaxVec, -1, "multi_axpy: nvec out of range");
+  multi_axpy_kernel<<<grid_for(n), kThreads, 0, s>>>(nvec, X, ldx, c, y, n);
+  QTP_CHECK_LAUNCH();
+}
+
+void sub(hipStream_t s, const double* x, const double* y, double* z, int64_t n) {
+  sub_kernel<<<grid_for(n), kThreads, 0, s>>>(x, y, z, n);
+  QTP_CHECK_LAUNCH();
+}
+
+void add_inplace(hipStream_t s, const double* x, double* y, int64_t n) {
+  add_kernel<<<grid_for(n), kThreads, 0, s>>>(x, y, n);
+  QTP_CHECK_LAUNCH();
+}
+
+void any_nonfinite(hipStream_t s, const double* x, int64_t n, int* out) {
+  nonfinite_kernel<<<grid_for(n), kThreads, 0, s>>>(x, n, out);
+  QTP_CHECK_LAUNCH();
+}
+
+void bj_factor(hipStream_t s, int nslots, const int32_t* rp, const int32_t* col,
+               const double* val, double* Linv, int* bad) {
+  if (nslots <= 0) return;
+  bj_factor_kernel<<<div_up(nslots, 256), 256, 0, s>>>(nslots, rp, col, val,
+                                                       Linv, bad);
+  QTP_CHECK_LAUNCH();
+}
+
+void bj_apply(hipStream_t s, int nslots, int64_t n, const double* Linv, int trans,
+              const double* x, double* y) {
+  const int64_t tail = n - 3 * (int64_t)nslots;
+  const int64_t threads = (int64_t)nslots + tail;
+  bj_apply_kernel<<<div_up(threads, 256), 256, 0, s>>>(nslots, n, Linv, trans, x,
+                                                       y);
+  QTP_CHECK_LAUNCH();
+}
+
+void bj_scale_matrix(hipStream_t s, int nslots, const int32_t* rp,
+                     const int32_t* col, const double* val, const double* Linv,
+                     double* vout) {
+  if (nslots <= 0) return;
+  bj_scale_matrix_kernel<<<nslots, 64, 0, s>>>(nslots, rp, col, val, Linv, vout);
+  QTP_CHECK_LAUNCH();
+}
+
+}  // namespace qtp
