@@ -152,6 +152,17 @@ qtp_status qtp_newton_solve(qtp_ctx ctx, const double* rhs, double* x,
 /* Applies the current preconditioner: z = L^-T X L^-1 v. */
 qtp_status qtp_precond_apply(qtp_ctx ctx, const double* v, double* z);
 
+typedef struct {
+  int ns_iterations;      /* Newton-Schulz iterations run by the last build */
+  double probe_residual;  /* max over the two probes of rms(z - S~ X z) */
+  int max_rank_s;         /* largest rank of the compressed S~ */
+  int max_rank_x;         /* largest rank of X */
+  double ms;              /* wall time of the last build */
+} qtp_precond_stats;
+
+/* Statistics of the last qtp_precond_build on this context. */
+qtp_status qtp_get_precond_stats(qtp_ctx ctx, qtp_precond_stats* out);
+
 /* Ranks of the current compressed matrix (which = 0) or inverse (which = 1):
  * writes up to d+1 ints into ranks_host and returns d, or a negative status. */
 int qtp_get_qtt_ranks(qtp_ctx ctx, int which, int32_t* ranks_host);

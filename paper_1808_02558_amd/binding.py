@@ -53,6 +53,12 @@ class SolveStats(ctypes.Structure):
                 ("ms", ctypes.c_double)]
 
 
+class PrecondStats(ctypes.Structure):
+    _fields_ = [("ns_iterations", ctypes.c_int), ("probe_residual", ctypes.c_double),
+                ("max_rank_s", ctypes.c_int), ("max_rank_x", ctypes.c_int),
+                ("ms", ctypes.c_double)]
+
+
 _lib = None
 
 _P = ctypes.c_void_p
@@ -71,6 +77,7 @@ SIGNATURES = {
     "qtp_precond_load_qtt": (_I, [_P, _I, _P, _P]),
     "qtp_newton_solve": (_I, [_P, _P, _P, _P]),
     "qtp_precond_apply": (_I, [_P, _P, _P]),
+    "qtp_get_precond_stats": (_I, [_P, _P]),
     "qtp_get_qtt_ranks": (_I, [_P, _I, _P]),
     "qtp_get_qtt_cores": (_I, [_P, _I, _P, _I64]),
 }
@@ -181,6 +188,11 @@ class Context:
 
     def qtp_precond_apply(self, v, z):
         return self._check(self.lib.qtp_precond_apply(self.h, _ptr(v), _ptr(z)))
+
+    def qtp_get_precond_stats(self):
+        st = PrecondStats()
+        self._check(self.lib.qtp_get_precond_stats(self.h, ctypes.byref(st)))
+        return st
 
     def qtp_get_qtt_ranks(self, which):
         buf = (ctypes.c_int32 * 64)()

@@ -46,7 +46,7 @@ int64_t qtp::Qtt::total() const {
 
 void qtp::Ctx::check_cfg() {
   QTP_REQUIRE(cfg.precision >= 0 && cfg.precision <= 2, QTP_E_ARG, "bad precision");
-  QTP_REQUIRE(cfg.qtt_rmax >= 1 && cfg.qtt_rmax <= 256, QTP_E_ARG, "qtt_rmax out of [1,256]");
+  QTP_REQUIRE(cfg.qtt_rmax >= 1 && cfg.qtt_rmax <= 64, QTP_E_ARG, "qtt_rmax out of [1,64]");
   QTP_REQUIRE(cfg.qtt_rmax_s >= 1 && cfg.qtt_rmax_s <= 64, QTP_E_ARG, "qtt_rmax_s out of [1,64]");
   QTP_REQUIRE(cfg.qtt_eps > 0.0 && cfg.qtt_eps < 1.0, QTP_E_ARG, "qtt_eps out of (0,1)");
   QTP_REQUIRE(cfg.fgmres_restart >= 1 && cfg.fgmres_restart <= 63, QTP_E_ARG,
@@ -192,16 +192,43 @@ qtp_status qtp_set_newton_matrix(qtp_ctx ctx, int log2n, const int32_t* row_ptr,
     QTP_HIP(hipStreamSynchronize(c.stream));
     c.have_matrix = true;
     c.have_precond = false;
+    c.pat.valid = false;
     return QTP_OK;
   });
 }
 
 qtp_status qtp_precond_build(qtp_ctx ctx, int hot) {
   return guarded(ctx, [&](Ctx& c) {
+    hipEvent_t e0, e1;
+    QTP_HIP(hipEventCreate(&e0));
+    QTP_HIP(hipEventCreate(&e1));
+    QTP_HIP(hipEventRecord(e0, c.stream));
     qtp::precond_factor(c);
     c.have_precond = true;
     qtp::build_inverse(c, hot);
-    QTP_HIP(hipStreamSynchronize(c.stream));
+    QTP_HIP(hipEventRecord(e1, c.stream));
+    QTP_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    QTP_HIP(hipEventElapsedTime(&ms, e0, e1));
+    c.build_ms = ms;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return QTP_OK;
+  });
+}
+
+qtp_status qtp_get_precond_stats(qtp_ctx ctx, qtp_precond_stats* out) {
+  return guarded(ctx, [&](Ctx& c) {
+    QTP_REQUIRE(out, QTP_E_ARG, "null pointer");
+    QTP_REQUIRE(c.have_inverse, QTP_E_STATE, "no preconditioner built");
+    out->ns_iterations = c.ns_done;
+    out->probe_residual = c.probe_residual;
+    int ms = 0, mx = 0;
+    for (int r : c.A.ranks) ms = r > ms ? r : ms;
+    for (int r : c.X.ranks) mx = r > mx ? r : mx;
+    out->max_rank_s = ms;
+    out->max_rank_x = mx;
+    out->ms = c.build_ms;
     return QTP_OK;
   });
 }

@@ -20,6 +20,19 @@ struct Qtt {
   int64_t total() const;
 };
 
+// z-order (interleaved row/column bits) structure of the scaled matrix: the
+// sorted entries and, per tree level k, the non-zero blocks (rows of the
+// level-k unfolding) with the map from the finer level to them.
+struct Pattern {
+  bool valid = false;
+  int d = 0;
+  int64_t nent = 0, nval = 0;
+  DevBuf keys, perm;
+  std::vector<int64_t> nrows;   // rows of W_k, k = 1..d
+  std::vector<DevBuf> seg;      // seg[k]: finer item -> row of W_k
+  std::vector<DevBuf> rowkey;   // rowkey[k]: z prefix of each row of W_k
+};
+
 struct Ctx {
   qtp_config cfg{};
   hipStream_t stream = nullptr;
@@ -40,6 +53,10 @@ struct Ctx {
   Qtt X;              // approximate inverse
   bool have_precond = false;
   bool have_inverse = false;
+  Pattern pat;
+  int ns_done = 0;              // Newton-Schulz iterations of the last build
+  double probe_residual = 0.0;  // rms of z - S~ X z over the probes
+  double build_ms = 0.0;
 
   // workspaces
   DevBuf qtt_work;
