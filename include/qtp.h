@@ -163,6 +163,78 @@ typedef struct {
 /* Statistics of the last qtp_precond_build on this context. */
 qtp_status qtp_get_precond_stats(qtp_ctx ctx, qtp_precond_stats* out);
 
+/* ---------------------------------------------------------------------------
+ * One time step of frictional contact dynamics (Sec. 2.1-2.4, 3.3).
+ * ------------------------------------------------------------------------- */
+
+/* Copies M spheres into the context (Sec. 2.1): x, v, w [M][3] double (centre,
+ * velocity, angular velocity), radius [M], mass [M] (device pointers). */
+qtp_status qtp_set_bodies(qtp_ctx ctx, int M, const double* x, const double* v,
+                          const double* w, const double* radius,
+                          const double* mass);
+
+/* Static container planes [nw][4]: unit normal n into the domain and offset o
+ * (inside: n.x - o >= 0).  Host pointer.  Walls have infinite mass. */
+qtp_status qtp_set_walls(qtp_ctx ctx, int nw, const double* planes_host);
+
+/* Friction coefficient mu (Sec. 2.2), step h, active-set threshold delta
+ * (A(q, delta) = {Phi <= delta}), gravity [3] (host), padded size 2^log2n. */
+qtp_status qtp_set_params(qtp_ctx ctx, double mu, double h, double delta,
+                          const double* gravity_host, int log2n);
+
+/* Contact detection (Sec. 2.2) and ordering (Sec. 3.3).  Writes the number of
+ * contacts.  QTP_E_CAPACITY when they exceed floor(2^log2n / 3) slots. */
+qtp_status qtp_detect(qtp_ctx ctx, int* n_contacts);
+
+/* Copies the ordered contacts out (device buffers of nc entries): a, b
+ * (int32; b >= M means wall b - M), phi [nc], frame [nc][9] (rows n, t1, t2),
+ * key [nc] (uint64 Morton key), slot [nc] (int32).  Any pointer may be NULL. */
+qtp_status qtp_get_contacts(qtp_ctx ctx, int32_t* a, int32_t* b, double* phi,
+                            double* frame, uint64_t* key, int32_t* slot);
+
+/* Assembles N = D^T M^-1 D and r = b + D^T M^-1 k (Sec. 2.3) in scaled units
+ * (N * m_bar, r / (g h)) on the slot layout.  Follows qtp_detect. */
+qtp_status qtp_assemble(qtp_ctx ctx);
+
+/* Copies the assembled QP out: BSR3 pattern (row_ptr [S+1], col [nnzb]),
+ * values of N [nnzb*9] and r [2^d]; returns nnzb through *nnzb (host). Any
+ * array pointer may be NULL to query nnzb only. */
+qtp_status qtp_get_qp(qtp_ctx ctx, int32_t* row_ptr, int32_t* col, double* valN,
+                      double* r, int64_t* nnzb);
+
+typedef struct {
+  int n_contacts;
+  int pdip_iterations;
+  int converged;
+  int fgmres_iterations;   /* total over the Newton steps */
+  int max_fgmres;          /* largest count of one Newton step */
+  double gap;              /* final eta / m */
+  double dual_inf;         /* final |r_dual|_inf, scaled units */
+  double ms_detect, ms_assemble, ms_precond, ms_solve, ms_pdip, ms_integrate;
+  double ms_total;
+  double newton_solve_ms_median;
+} qtp_step_stats;
+
+/* PDIP on the assembled QP (Sec. 2.4 with the Schur-complement Newton system
+ * of Sec. 3.3; each Newton step solved by qtp_newton_solve's method with the
+ * QTT preconditioner built on the first step and hot-started afterwards).
+ * Start: gamma = (1, 0, 0) per contact in scaled units (Sec. 3.3).  Returns
+ * QTP_NOT_CONVERGED when pdip_maxit is reached. */
+qtp_status qtp_pdip_solve(qtp_ctx ctx, qtp_step_stats* stats);
+
+/* Impulses of the last PDIP solve in the contact frame, physical units
+ * (N s): [nc][3] double. */
+qtp_status qtp_get_impulses(qtp_ctx ctx, double* gamma);
+
+/* Semi-implicit update (Sec. 2.2): v += M^-1 (h f + D gamma), x += h v. */
+qtp_status qtp_integrate(qtp_ctx ctx);
+
+/* Copies the body state out: x, v, w [M][3] (any may be NULL). */
+qtp_status qtp_get_state(qtp_ctx ctx, double* x, double* v, double* w);
+
+/* detect + assemble + PDIP + integrate. */
+qtp_status qtp_step(qtp_ctx ctx, qtp_step_stats* stats);
+
 /* Ranks of the current compressed matrix (which = 0) or inverse (which = 1):
  * writes up to d+1 ints into ranks_host and returns d, or a negative status. */
 int qtp_get_qtt_ranks(qtp_ctx ctx, int which, int32_t* ranks_host);

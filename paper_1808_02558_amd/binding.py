@@ -59,6 +59,17 @@ class PrecondStats(ctypes.Structure):
                 ("ms", ctypes.c_double)]
 
 
+class StepStats(ctypes.Structure):
+    _fields_ = [("n_contacts", ctypes.c_int), ("pdip_iterations", ctypes.c_int),
+                ("converged", ctypes.c_int), ("fgmres_iterations", ctypes.c_int),
+                ("max_fgmres", ctypes.c_int), ("gap", ctypes.c_double),
+                ("dual_inf", ctypes.c_double), ("ms_detect", ctypes.c_double),
+                ("ms_assemble", ctypes.c_double), ("ms_precond", ctypes.c_double),
+                ("ms_solve", ctypes.c_double), ("ms_pdip", ctypes.c_double),
+                ("ms_integrate", ctypes.c_double), ("ms_total", ctypes.c_double),
+                ("newton_solve_ms_median", ctypes.c_double)]
+
+
 _lib = None
 
 _P = ctypes.c_void_p
@@ -78,6 +89,19 @@ SIGNATURES = {
     "qtp_newton_solve": (_I, [_P, _P, _P, _P]),
     "qtp_precond_apply": (_I, [_P, _P, _P]),
     "qtp_get_precond_stats": (_I, [_P, _P]),
+    "qtp_set_bodies": (_I, [_P, _I, _P, _P, _P, _P, _P]),
+    "qtp_set_walls": (_I, [_P, _I, _P]),
+    "qtp_set_params": (_I, [_P, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                            _P, _I]),
+    "qtp_detect": (_I, [_P, _P]),
+    "qtp_get_contacts": (_I, [_P, _P, _P, _P, _P, _P, _P]),
+    "qtp_assemble": (_I, [_P]),
+    "qtp_get_qp": (_I, [_P, _P, _P, _P, _P, _P]),
+    "qtp_pdip_solve": (_I, [_P, _P]),
+    "qtp_get_impulses": (_I, [_P, _P]),
+    "qtp_integrate": (_I, [_P]),
+    "qtp_get_state": (_I, [_P, _P, _P, _P]),
+    "qtp_step": (_I, [_P, _P]),
     "qtp_get_qtt_ranks": (_I, [_P, _I, _P]),
     "qtp_get_qtt_cores": (_I, [_P, _I, _P, _I64]),
 }
@@ -193,6 +217,86 @@ class Context:
         st = PrecondStats()
         self._check(self.lib.qtp_get_precond_stats(self.h, ctypes.byref(st)))
         return st
+
+    # ---- time step -------------------------------------------------------
+    def qtp_set_bodies(self, x, v, w, radius, mass):
+        M = int(radius.numel())
+        return self._check(self.lib.qtp_set_bodies(
+            self.h, M, _ptr(x), _ptr(v), _ptr(w), _ptr(radius), _ptr(mass)))
+
+    def qtp_set_walls(self, planes):
+        import numpy as np
+        p = np.ascontiguousarray(planes, dtype=np.float64).reshape(-1, 4)
+        return self._check(self.lib.qtp_set_walls(
+            self.h, int(p.shape[0]), p.ctypes.data_as(ctypes.c_void_p)))
+
+    def qtp_set_params(self, mu, h, delta, gravity, log2n):
+        g = (ctypes.c_double * 3)(*[float(v) for v in gravity])
+        return self._check(self.lib.qtp_set_params(
+            self.h, float(mu), float(h), float(delta), g, int(log2n)))
+
+    def qtp_detect(self):
+        nc = ctypes.c_int()
+        self._check(self.lib.qtp_detect(self.h, ctypes.byref(nc)))
+        return nc.value
+
+    def qtp_get_contacts(self, nc):
+        import torch
+        dev = "cuda"
+        a = torch.empty(nc, dtype=torch.int32, device=dev)
+        b = torch.empty(nc, dtype=torch.int32, device=dev)
+        phi = torch.empty(nc, dtype=torch.float64, device=dev)
+        frame = torch.empty(nc, 9, dtype=torch.float64, device=dev)
+        key = torch.empty(nc, dtype=torch.int64, device=dev)
+        slot = torch.empty(nc, dtype=torch.int32, device=dev)
+        self._check(self.lib.qtp_get_contacts(self.h, _ptr(a), _ptr(b), _ptr(phi),
+                                              _ptr(frame), _ptr(key), _ptr(slot)))
+        return dict(a=a, b=b, phi=phi, frame=frame, key=key, slot=slot)
+
+    def qtp_assemble(self):
+        return self._check(self.lib.qtp_assemble(self.h))
+
+    def qtp_get_qp(self, log2n):
+        import torch
+        nnzb = ctypes.c_int64()
+        self._check(self.lib.qtp_get_qp(self.h, None, None, None, None,
+                                        ctypes.byref(nnzb)))
+        n = 1 << log2n
+        rp = torch.empty(n // 3 + 1, dtype=torch.int32, device="cuda")
+        col = torch.empty(nnzb.value, dtype=torch.int32, device="cuda")
+        val = torch.empty(9 * nnzb.value, dtype=torch.float64, device="cuda")
+        r = torch.empty(n, dtype=torch.float64, device="cuda")
+        self._check(self.lib.qtp_get_qp(self.h, _ptr(rp), _ptr(col), _ptr(val),
+                                        _ptr(r), ctypes.byref(nnzb)))
+        return rp, col, val, r
+
+    def qtp_pdip_solve(self):
+        st = StepStats()
+        rc = self._check(self.lib.qtp_pdip_solve(self.h, ctypes.byref(st)),
+                         allow_nc=True)
+        return rc, st
+
+    def qtp_get_impulses(self, nc):
+        import torch
+        g = torch.empty(nc, 3, dtype=torch.float64, device="cuda")
+        self._check(self.lib.qtp_get_impulses(self.h, _ptr(g)))
+        return g
+
+    def qtp_integrate(self):
+        return self._check(self.lib.qtp_integrate(self.h))
+
+    def qtp_get_state(self, M):
+        import torch
+        x = torch.empty(M, 3, dtype=torch.float64, device="cuda")
+        v = torch.empty(M, 3, dtype=torch.float64, device="cuda")
+        w = torch.empty(M, 3, dtype=torch.float64, device="cuda")
+        self._check(self.lib.qtp_get_state(self.h, _ptr(x), _ptr(v), _ptr(w)))
+        return x, v, w
+
+    def qtp_step(self):
+        st = StepStats()
+        rc = self._check(self.lib.qtp_step(self.h, ctypes.byref(st)), allow_nc=True)
+        return rc, st
 
     def qtp_get_qtt_ranks(self, which):
         buf = (ctypes.c_int32 * 64)()

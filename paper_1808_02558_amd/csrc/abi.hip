@@ -1,6 +1,7 @@
 // C-ABI of the qtp library: argument checks, context management, and the
 // translation of internal errors into qtp_status codes.  Nothing here
 // computes; every step runs in the kernels of the other files.
+#include <chrono>
 #include <cstring>
 
 #include "context.h"
@@ -274,6 +275,189 @@ qtp_status qtp_precond_apply(qtp_ctx ctx, const double* v, double* z) {
     qtp::precond_apply(c, v, z);
     QTP_HIP(hipStreamSynchronize(c.stream));
     return QTP_OK;
+  });
+}
+
+qtp_status qtp_set_bodies(qtp_ctx ctx, int M, const double* x, const double* v,
+                          const double* w, const double* radius,
+                          const double* mass) {
+  return guarded(ctx, [&](Ctx& c) {
+    QTP_REQUIRE(M >= 1 && M < (1 << 30), QTP_E_ARG, "M out of range");
+    QTP_REQUIRE(x && v && w && radius && mass, QTP_E_ARG, "null pointer");
+    qtp::Scene& sc = c.scene;
+    sc.M = M;
+    const size_t b3 = sizeof(double) * 3 * (size_t)M, b1 = sizeof(double) * M;
+    sc.x.ensure(b3);
+    sc.v.ensure(b3);
+    sc.w.ensure(b3);
+    sc.radius.ensure(b1);
+    sc.mass.ensure(b1);
+    QTP_HIP(hipMemcpyAsync(sc.x.get(), x, b3, hipMemcpyDeviceToDevice, c.stream));
+    QTP_HIP(hipMemcpyAsync(sc.v.get(), v, b3, hipMemcpyDeviceToDevice, c.stream));
+    QTP_HIP(hipMemcpyAsync(sc.w.get(), w, b3, hipMemcpyDeviceToDevice, c.stream));
+    QTP_HIP(hipMemcpyAsync(sc.radius.get(), radius, b1, hipMemcpyDeviceToDevice, c.stream));
+    QTP_HIP(hipMemcpyAsync(sc.mass.get(), mass, b1, hipMemcpyDeviceToDevice, c.stream));
+    QTP_HIP(hipStreamSynchronize(c.stream));
+    c.ct.valid = false;
+    c.qp.valid = false;
+    return QTP_OK;
+  });
+}
+
+qtp_status qtp_set_walls(qtp_ctx ctx, int nw, const double* planes_host) {
+  return guarded(ctx, [&](Ctx& c) {
+    QTP_REQUIRE(nw >= 0 && nw <= 1024, QTP_E_ARG, "nw out of [0,1024]");
+    QTP_REQUIRE(nw == 0 || planes_host, QTP_E_ARG, "null planes");
+    c.scene.nw = nw;
+    c.scene.planes.ensure(sizeof(double) * 4 * (size_t)(nw > 0 ? nw : 1));
+    if (nw > 0)
+      QTP_HIP(hipMemcpyAsync(c.scene.planes.get(), planes_host, sizeof(double) * 4 * nw,
+                             hipMemcpyHostToDevice, c.stream));
+    QTP_HIP(hipStreamSynchronize(c.stream));
+    c.ct.valid = false;
+    return QTP_OK;
+  });
+}
+
+qtp_status qtp_set_params(qtp_ctx ctx, double mu, double h, double delta,
+                          const double* gravity_host, int log2n) {
+  return guarded(ctx, [&](Ctx& c) {
+    QTP_REQUIRE(mu > 0.0 && h > 0.0 && delta >= 0.0, QTP_E_ARG, "mu, h > 0, delta >= 0");
+    QTP_REQUIRE(gravity_host, QTP_E_ARG, "null gravity");
+    QTP_REQUIRE(valid_d(log2n) && log2n <= 26, QTP_E_ARG, "log2n out of [2,26]");
+    qtp::Scene& sc = c.scene;
+    sc.mu = mu;
+    sc.h = h;
+    sc.delta = delta;
+    for (int k = 0; k < 3; ++k) sc.g[k] = gravity_host[k];
+    sc.log2n = log2n;
+    sc.have_params = true;
+    c.ct.valid = false;
+    return QTP_OK;
+  });
+}
+
+qtp_status qtp_detect(qtp_ctx ctx, int* n_contacts) {
+  return guarded(ctx, [&](Ctx& c) {
+    QTP_REQUIRE(c.scene.have_params && c.scene.M > 0, QTP_E_STATE,
+                "set bodies and params first");
+    const int nc = qtp::detect_contacts(c);
+    if (n_contacts) *n_contacts = nc;
+    return QTP_OK;
+  });
+}
+
+qtp_status qtp_get_contacts(qtp_ctx ctx, int32_t* a, int32_t* b, double* phi,
+                            double* frame, uint64_t* key, int32_t* slot) {
+  return guarded(ctx, [&](Ctx& c) {
+    QTP_REQUIRE(c.ct.valid, QTP_E_STATE, "no contacts detected");
+    const int nc = c.ct.nc;
+    auto cp = [&](void* dst, const qtp::DevBuf& src, size_t es) {
+      if (dst && nc > 0)
+        QTP_HIP(hipMemcpyAsync(dst, src.get(), es * nc, hipMemcpyDeviceToDevice, c.stream));
+    };
+    cp(a, c.ct.a, sizeof(int32_t));
+    cp(b, c.ct.b, sizeof(int32_t));
+    cp(phi, c.ct.phi, sizeof(double));
+    cp(frame, c.ct.frame, 9 * sizeof(double));
+    cp(key, c.ct.key, sizeof(uint64_t));
+    cp(slot, c.ct.slot, sizeof(int32_t));
+    QTP_HIP(hipStreamSynchronize(c.stream));
+    return QTP_OK;
+  });
+}
+
+qtp_status qtp_assemble(qtp_ctx ctx) {
+  return guarded(ctx, [&](Ctx& c) {
+    qtp::assemble_qp(c);
+    return QTP_OK;
+  });
+}
+
+qtp_status qtp_get_qp(qtp_ctx ctx, int32_t* row_ptr, int32_t* col, double* valN,
+                      double* r, int64_t* nnzb) {
+  return guarded(ctx, [&](Ctx& c) {
+    QTP_REQUIRE(c.qp.valid, QTP_E_STATE, "no assembled QP");
+    const int64_t n = (int64_t)1 << c.scene.log2n;
+    const int ns = (int)(n / 3);
+    if (nnzb) *nnzb = c.qp.nnzb;
+    if (row_ptr)
+      QTP_HIP(hipMemcpyAsync(row_ptr, c.qp.rp.get(), sizeof(int32_t) * (ns + 1),
+                             hipMemcpyDeviceToDevice, c.stream));
+    if (col)
+      QTP_HIP(hipMemcpyAsync(col, c.qp.col.get(), sizeof(int32_t) * c.qp.nnzb,
+                             hipMemcpyDeviceToDevice, c.stream));
+    if (valN)
+      QTP_HIP(hipMemcpyAsync(valN, c.qp.valN.get(), sizeof(double) * 9 * c.qp.nnzb,
+                             hipMemcpyDeviceToDevice, c.stream));
+    if (r)
+      QTP_HIP(hipMemcpyAsync(r, c.qp.r.get(), sizeof(double) * n,
+                             hipMemcpyDeviceToDevice, c.stream));
+    QTP_HIP(hipStreamSynchronize(c.stream));
+    return QTP_OK;
+  });
+}
+
+qtp_status qtp_pdip_solve(qtp_ctx ctx, qtp_step_stats* stats) {
+  return guarded(ctx, [&](Ctx& c) {
+    qtp_step_stats local{};
+    qtp_step_stats* st = stats ? stats : &local;
+    return qtp::pdip_solve(c, st);
+  });
+}
+
+qtp_status qtp_get_impulses(qtp_ctx ctx, double* gamma) {
+  return guarded(ctx, [&](Ctx& c) {
+    QTP_REQUIRE(gamma, QTP_E_ARG, "null pointer");
+    qtp::gather_impulses(c, gamma);
+    return QTP_OK;
+  });
+}
+
+qtp_status qtp_integrate(qtp_ctx ctx) {
+  return guarded(ctx, [&](Ctx& c) {
+    qtp::integrate(c);
+    return QTP_OK;
+  });
+}
+
+qtp_status qtp_get_state(qtp_ctx ctx, double* x, double* v, double* w) {
+  return guarded(ctx, [&](Ctx& c) {
+    QTP_REQUIRE(c.scene.M > 0, QTP_E_STATE, "no bodies");
+    const size_t b3 = sizeof(double) * 3 * (size_t)c.scene.M;
+    if (x) QTP_HIP(hipMemcpyAsync(x, c.scene.x.get(), b3, hipMemcpyDeviceToDevice, c.stream));
+    if (v) QTP_HIP(hipMemcpyAsync(v, c.scene.v.get(), b3, hipMemcpyDeviceToDevice, c.stream));
+    if (w) QTP_HIP(hipMemcpyAsync(w, c.scene.w.get(), b3, hipMemcpyDeviceToDevice, c.stream));
+    QTP_HIP(hipStreamSynchronize(c.stream));
+    return QTP_OK;
+  });
+}
+
+qtp_status qtp_step(qtp_ctx ctx, qtp_step_stats* stats) {
+  return guarded(ctx, [&](Ctx& c) {
+    QTP_REQUIRE(c.scene.have_params && c.scene.M > 0, QTP_E_STATE,
+                "set bodies and params first");
+    qtp_step_stats local{};
+    qtp_step_stats* st = stats ? stats : &local;
+    using clk = std::chrono::steady_clock;
+    auto ms = [](clk::time_point a, clk::time_point b) {
+      return std::chrono::duration<double, std::milli>(b - a).count();
+    };
+    const auto t0 = clk::now();
+    qtp::detect_contacts(c);
+    const auto t1 = clk::now();
+    qtp::assemble_qp(c);
+    const auto t2 = clk::now();
+    const int rc = qtp::pdip_solve(c, st);
+    const auto t3 = clk::now();
+    qtp::integrate(c);
+    const auto t4 = clk::now();
+    st->ms_detect = ms(t0, t1);
+    st->ms_assemble = ms(t1, t2);
+    st->ms_pdip = ms(t2, t3);
+    st->ms_integrate = ms(t3, t4);
+    st->ms_total = ms(t0, t4);
+    return rc;
   });
 }
 

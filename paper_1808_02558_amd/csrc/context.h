@@ -33,10 +33,56 @@ struct Pattern {
   std::vector<DevBuf> rowkey;   // rowkey[k]: z prefix of each row of W_k
 };
 
+// Bodies, walls and step parameters of one time step (library copies).
+struct Scene {
+  int M = 0, nw = 0;
+  DevBuf x, v, w, radius, mass, planes;
+  double mu = 0.5, h = 1e-3, delta = 0.0;
+  double g[3] = {0.0, 0.0, -9.81};
+  int log2n = 0;
+  bool have_params = false;
+};
+
+// The ordered active set: a, b (b >= M: wall b - M), gap, frame rows
+// (n, t1, t2), Morton key and slot of each contact.
+struct Contacts {
+  int nc = 0;
+  int npairs = 0;
+  bool valid = false;
+  DevBuf a, b, key, phi, frame, slot, bounds;
+  DevBuf cell_key, cell_idx, cell_start, cell_stop;
+};
+
+// The QP of Sec. 2.3 in scaled units on the slot layout: N (BSR3, with
+// identity dummy blocks), r (padded), and the body -> contact incidence.
+struct Qp {
+  bool valid = false;
+  double mbar = 0.0, vbar = 0.0, gbar = 0.0;  // mass, velocity, impulse scales
+  int64_t nnzb = 0;
+  DevBuf rp, col, valN, r, diagpos, inv_slot;
+  DevBuf body_ptr, body_ent;  // incidence: (contact << 1) | (role A)
+};
+
+// PDIP iterate and work vectors.
+struct Pdip {
+  DevBuf gamma, dgamma, u, wv, rhs;   // padded [n]
+  DevBuf lam, dlam;                    // [2 nc]: cone part then gamma_n part
+  DevBuf part;                         // reduction partials
+  bool have_gamma = false;
+};
+
 struct Ctx {
   qtp_config cfg{};
   hipStream_t stream = nullptr;
   std::string err;
+
+  Scene scene;
+  Contacts ct;
+  Qp qp;
+  Pdip pd;
+  // temporaries of detection and assembly
+  DevBuf tmp1, cnt, offs, cnt2, offs2, ua, ub, pk, perm, perm2;
+  DevBuf sk, sv, sh, ss;  // sort and scan scratch
 
   // Newton matrix (BSR3)
   int log2n = 0;
@@ -74,5 +120,11 @@ void precond_factor(Ctx& c);          // block-Jacobi factors of the matrix
 void ensure_lp_cores(Ctx& c, Qtt& q);  // reduced-precision copy of q
 // QTT construction (qtt_build.hip)
 void build_inverse(Ctx& c, int hot);
+// Time step (contacts.hip, assembly.hip, pdip.hip)
+int detect_contacts(Ctx& c);
+void assemble_qp(Ctx& c);
+int pdip_solve(Ctx& c, qtp_step_stats* st);
+void integrate(Ctx& c);
+void gather_impulses(Ctx& c, double* out);
 
 }  // namespace qtp
