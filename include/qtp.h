@@ -235,6 +235,20 @@ qtp_status qtp_get_state(qtp_ctx ctx, double* x, double* v, double* w);
 /* detect + assemble + PDIP + integrate. */
 qtp_status qtp_step(qtp_ctx ctx, qtp_step_stats* stats);
 
+/* ---------------------------------------------------------------------------
+ * Measurement hooks.
+ * ------------------------------------------------------------------------- */
+
+/* Enables (1) or disables (0) event timing of the Newton-step kernels on the
+ * context's stream and clears the accumulated times.  Timed groups:
+ * "bsr_spmv" (one sparse product), "qtt_apply" (one QTT product, all
+ * levels), "cgs2" (one Arnoldi orthogonalisation). */
+qtp_status qtp_profile(qtp_ctx ctx, int enable);
+
+/* Total milliseconds and launch count of a timed group since qtp_profile. */
+qtp_status qtp_get_kernel_time(qtp_ctx ctx, const char* name, double* ms_total,
+                               int64_t* launches);
+
 /* Ranks of the current compressed matrix (which = 0) or inverse (which = 1):
  * writes up to d+1 ints into ranks_host and returns d, or a negative status. */
 int qtp_get_qtt_ranks(qtp_ctx ctx, int which, int32_t* ranks_host);

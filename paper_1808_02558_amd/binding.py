@@ -102,6 +102,8 @@ SIGNATURES = {
     "qtp_integrate": (_I, [_P]),
     "qtp_get_state": (_I, [_P, _P, _P, _P]),
     "qtp_step": (_I, [_P, _P]),
+    "qtp_profile": (_I, [_P, _I]),
+    "qtp_get_kernel_time": (_I, [_P, ctypes.c_char_p, _P, _P]),
     "qtp_get_qtt_ranks": (_I, [_P, _I, _P]),
     "qtp_get_qtt_cores": (_I, [_P, _I, _P, _I64]),
 }
@@ -297,6 +299,16 @@ class Context:
         st = StepStats()
         rc = self._check(self.lib.qtp_step(self.h, ctypes.byref(st)), allow_nc=True)
         return rc, st
+
+    def qtp_profile(self, enable=True):
+        return self._check(self.lib.qtp_profile(self.h, int(bool(enable))))
+
+    def qtp_get_kernel_time(self, name):
+        ms = ctypes.c_double()
+        cnt = ctypes.c_int64()
+        self._check(self.lib.qtp_get_kernel_time(self.h, name.encode(),
+                                                 ctypes.byref(ms), ctypes.byref(cnt)))
+        return ms.value, cnt.value
 
     def qtp_get_qtt_ranks(self, which):
         buf = (ctypes.c_int32 * 64)()

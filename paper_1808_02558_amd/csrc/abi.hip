@@ -45,6 +45,28 @@ int64_t qtp::Qtt::total() const {
   return t;
 }
 
+qtp::KTimer& qtp::Ctx::timer(const char* name) {
+  for (auto& kv : timers)
+    if (kv.first == name) return kv.second;
+  timers.emplace_back(name, KTimer{});
+  return timers.back().second;
+}
+
+void qtp::Ctx::flush_timers() {
+  for (auto& kv : timers) {
+    for (auto& e : kv.second.pending) {
+      QTP_HIP(hipEventSynchronize(e.second));
+      float ms = 0.f;
+      QTP_HIP(hipEventElapsedTime(&ms, e.first, e.second));
+      kv.second.ms += ms;
+      kv.second.count += 1;
+      (void)hipEventDestroy(e.first);
+      (void)hipEventDestroy(e.second);
+    }
+    kv.second.pending.clear();
+  }
+}
+
 void qtp::Ctx::check_cfg() {
   QTP_REQUIRE(cfg.precision >= 0 && cfg.precision <= 2, QTP_E_ARG, "bad precision");
   QTP_REQUIRE(cfg.qtt_rmax >= 1 && cfg.qtt_rmax <= 64, QTP_E_ARG, "qtt_rmax out of [1,64]");
@@ -109,6 +131,10 @@ void qtp_destroy(qtp_ctx ctx) {
   if (!ctx) return;
   if (ctx->c.stream) (void)hipStreamSynchronize(ctx->c.stream);
   else (void)hipDeviceSynchronize();
+  try {
+    ctx->c.flush_timers();
+  } catch (...) {
+  }
   delete ctx;
 }
 
@@ -458,6 +484,31 @@ qtp_status qtp_step(qtp_ctx ctx, qtp_step_stats* stats) {
     st->ms_integrate = ms(t3, t4);
     st->ms_total = ms(t0, t4);
     return rc;
+  });
+}
+
+qtp_status qtp_profile(qtp_ctx ctx, int enable) {
+  return guarded(ctx, [&](Ctx& c) {
+    c.flush_timers();
+    c.timers.clear();
+    c.profile = enable != 0;
+    return QTP_OK;
+  });
+}
+
+qtp_status qtp_get_kernel_time(qtp_ctx ctx, const char* name, double* ms_total,
+                               int64_t* launches) {
+  return guarded(ctx, [&](Ctx& c) {
+    QTP_REQUIRE(name && ms_total && launches, QTP_E_ARG, "null pointer");
+    c.flush_timers();
+    *ms_total = 0.0;
+    *launches = 0;
+    for (auto& kv : c.timers)
+      if (kv.first == name) {
+        *ms_total = kv.second.ms;
+        *launches = kv.second.count;
+      }
+    return QTP_OK;
   });
 }
 

@@ -71,8 +71,19 @@ struct Pdip {
   bool have_gamma = false;
 };
 
+// Optional event timing of selected kernels on the context's stream.
+struct KTimer {
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+  double ms = 0.0;
+  int64_t count = 0;
+};
+
 struct Ctx {
   qtp_config cfg{};
+  bool profile = false;
+  std::vector<std::pair<std::string, KTimer>> timers;
+  KTimer& timer(const char* name);
+  void flush_timers();
   hipStream_t stream = nullptr;
   std::string err;
 
@@ -111,6 +122,25 @@ struct Ctx {
   DevBuf flag;                // int flags
 
   void check_cfg();
+};
+
+// Records events around a launch when the context profiles.
+struct TimedLaunch {
+  Ctx& c;
+  KTimer* t = nullptr;
+  hipEvent_t a = nullptr, b = nullptr;
+  TimedLaunch(Ctx& ctx, const char* name) : c(ctx) {
+    if (!c.profile) return;
+    t = &c.timer(name);
+    QTP_HIP(hipEventCreate(&a));
+    QTP_HIP(hipEventCreate(&b));
+    QTP_HIP(hipEventRecord(a, c.stream));
+  }
+  ~TimedLaunch() {
+    if (!t) return;
+    (void)hipEventRecord(b, c.stream);
+    t->pending.emplace_back(a, b);
+  }
 };
 
 // Solver entry points (solver.hip)

@@ -75,6 +75,7 @@ void ensure_krylov(Ctx& c, int m) {
 }
 
 void spmv(Ctx& c, const double* x, double* y) {
+  TimedLaunch tl(c, "bsr_spmv");
   bsr_spmv(c.stream, c.nslots, c.n, c.rp.as<int32_t>(), c.col.as<int32_t>(),
            c.val.as<double>(), x, y);
 }
@@ -124,9 +125,12 @@ int fgmres(Ctx& c, const double* rhs, double* x, qtp_solve_stats* st) {
       double* w = V + (int64_t)(j + 1) * n;
       precond_apply(c, vj, zj);
       spmv(c, zj, w);
-      multi_dot(c.stream, j + 1, V, n, w, n, part, sc);
-      cgs_update_dot(c.stream, j + 1, V, n, sc, w, n, part, sc + 64);
-      cgs_update_norm2(c.stream, j + 1, V, n, sc + 64, w, n, part, sc + 128);
+      {
+        TimedLaunch tl(c, "cgs2");
+        multi_dot(c.stream, j + 1, V, n, w, n, part, sc);
+        cgs_update_dot(c.stream, j + 1, V, n, sc, w, n, part, sc + 64);
+        cgs_update_norm2(c.stream, j + 1, V, n, sc + 64, w, n, part, sc + 128);
+      }
       QTP_HIP(hipMemcpyAsync(hbuf.data(), sc, sizeof(double) * 129,
                              hipMemcpyDeviceToHost, c.stream));
       QTP_HIP(hipStreamSynchronize(c.stream));
@@ -244,6 +248,7 @@ void precond_apply(Ctx& c, const double* v, double* z) {
       cores = X.cores_lp.get();
     }
     c.qtt_work.ensure(qtt_apply_workspace(X.d, X.ranks.data(), c.cfg.precision));
+    TimedLaunch tl(c, "qtt_apply");
     qtt_apply(c.stream, X.d, X.ranks.data(), cores, c.cfg.precision, t1, t2,
               c.qtt_work.get());
     bj_apply(c.stream, c.nslots, c.n, c.Linv.as<double>(), 1, t2, z);
