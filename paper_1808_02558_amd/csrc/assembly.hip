@@ -367,10 +367,12 @@ void assemble_qp(Ctx& c) {
   }
   QTP_HIP(hipStreamSynchronize(s));
   qp.valid = true;
+  qp.stale = false;
 }
 
 void integrate(Ctx& c) {
-  QTP_REQUIRE(c.qp.valid && c.pd.have_gamma, QTP_E_STATE, "solve before integrate");
+  QTP_REQUIRE(c.qp.valid && !c.qp.stale && c.pd.have_gamma, QTP_E_STATE,
+              "solve before integrate");
   Scene& sc = c.scene;
   integrate_kernel<<<div_up(sc.M, kT), kT, 0, c.stream>>>(
       sc.M, sc.h, c.qp.gbar, make_double3(sc.g[0], sc.g[1], sc.g[2]),
@@ -381,7 +383,7 @@ void integrate(Ctx& c) {
   QTP_CHECK_LAUNCH();
   QTP_HIP(hipStreamSynchronize(c.stream));
   c.ct.valid = false;  // positions moved: contacts must be detected again
-  c.qp.valid = false;
+  c.qp.stale = true;  // the QP stays readable but belongs to the old positions
 }
 
 }  // namespace qtp

@@ -57,6 +57,7 @@ struct Contacts {
 // identity dummy blocks), r (padded), and the body -> contact incidence.
 struct Qp {
   bool valid = false;
+  bool stale = false;  // positions moved since assembly
   double mbar = 0.0, vbar = 0.0, gbar = 0.0;  // mass, velocity, impulse scales
   int64_t nnzb = 0;
   DevBuf rp, col, valN, r, diagpos, inv_slot;
@@ -78,7 +79,12 @@ struct KTimer {
   int64_t count = 0;
 };
 
+struct BuildCache;
+void destroy_build_cache(BuildCache* bc);
+
 struct Ctx {
+  ~Ctx() { destroy_build_cache(bcache); }
+  BuildCache* bcache = nullptr;  // persistent scratch of the QTT construction
   qtp_config cfg{};
   bool profile = false;
   std::vector<std::pair<std::string, KTimer>> timers;

@@ -108,17 +108,24 @@ __device__ inline int rr_partner(int pos, int round, int n) {
   return 1 + (pos - 1 + round) % (n - 1);
 }
 
+// NMAX > 0: A (n <= NMAX) is copied into LDS, and V too when V_LDS; the
+// rotations then run out of LDS.  NMAX == 0: both stay in global memory.
+template <int NMAX, bool V_LDS>
 __global__ __launch_bounds__(kEigThreads) void jacobi_eig_kernel(
-    int n, double* __restrict__ A, double* __restrict__ V, double* __restrict__ w,
+    int n, double* __restrict__ Ag, double* __restrict__ Vg, double* __restrict__ w,
     int max_sweeps, double tol) {
   __shared__ int pp[128], qq[128];
   __shared__ double cs[128], sn[128];
-  __shared__ int partner[256];
-  __shared__ double cside[256], sside[256];  // per index: c and signed s
   __shared__ double red[kEigThreads / 64];
   __shared__ int stop;
+  __shared__ double Al[NMAX > 0 ? NMAX * NMAX : 1];
+  __shared__ double Vl[V_LDS ? NMAX * NMAX : 1];
+  double* A = NMAX > 0 ? Al : Ag;
+  double* V = V_LDS ? Vl : Vg;
   const int tid = threadIdx.x;
   const int half = n / 2;
+  if (NMAX > 0)
+    for (int e = tid; e < n * n; e += kEigThreads) Al[e] = Ag[e];
   for (int e = tid; e < n * n; e += kEigThreads)
     V[e] = (e / n == e % n) ? 1.0 : 0.0;
   __syncthreads();
@@ -169,9 +176,6 @@ __global__ __launch_bounds__(kEigThreads) void jacobi_eig_kernel(
           s = t * c;
         }
         pp[tid] = p; qq[tid] = q; cs[tid] = c; sn[tid] = s;
-        partner[p] = q; partner[q] = p;
-        cside[p] = c; cside[q] = c;
-        sside[p] = s; sside[q] = s;
       }
       __syncthreads();
       // A <- J^T A J over all quads {p_i, q_i} x {p_j, q_j}
@@ -203,7 +207,8 @@ __global__ __launch_bounds__(kEigThreads) void jacobi_eig_kernel(
     }
   }
   for (int i = tid; i < n; i += kEigThreads) w[i] = A[i * n + i];
-  (void)partner; (void)cside; (void)sside;
+  if (V_LDS)
+    for (int e = tid; e < n * n; e += kEigThreads) Vg[e] = Vl[e];
 }
 
 // order[i] = index of the i-th largest eigenvalue (ties by index)
@@ -357,7 +362,12 @@ void gemm(hipStream_t s, int transA, int transB, int M, int N, int K,
 void sym_eig(hipStream_t s, int n, double* A, double* V, double* w,
              double* wsorted, double* Vsorted) {
   QTP_REQUIRE(n >= 2 && n <= 256 && n % 2 == 0, -1, "sym_eig: n must be even in [2,256]");
-  jacobi_eig_kernel<<<1, kEigThreads, 0, s>>>(n, A, V, w, 30, 1e-15);
+  if (n <= 64)
+    jacobi_eig_kernel<64, true><<<1, kEigThreads, 0, s>>>(n, A, V, w, 30, 1e-15);
+  else if (n <= 128)
+    jacobi_eig_kernel<128, false><<<1, kEigThreads, 0, s>>>(n, A, V, w, 30, 1e-15);
+  else
+    jacobi_eig_kernel<0, false><<<1, kEigThreads, 0, s>>>(n, A, V, w, 30, 1e-15);
   QTP_CHECK_LAUNCH();
   eig_sort_kernel<<<1, 256, 0, s>>>(n, w, V, wsorted, Vsorted);
   QTP_CHECK_LAUNCH();
@@ -366,20 +376,42 @@ void sym_eig(hipStream_t s, int n, double* A, double* V, double* w,
 void exclusive_scan(hipStream_t s, const int* in, int* out, int64_t n,
                     DevBuf& tmp) {
   if (n <= 0) return;
-  const int64_t ntile = (n + kScanTile - 1) / kScanTile;
-  tmp.ensure(sizeof(int) * (size_t)(2 * ntile + 2));
-  int* sums = tmp.as<int>();
-  int* offs = sums + ntile;
-  scan_tile_sums<<<(int)ntile, kScanT, 0, s>>>(in, n, sums);
-  QTP_CHECK_LAUNCH();
-  if (ntile == 1) {
-    QTP_HIP(hipMemsetAsync(offs, 0, sizeof(int), s));
-  } else {
-    DevBuf tmp2;
-    exclusive_scan(s, sums, offs, ntile, tmp2);
-    QTP_HIP(hipStreamSynchronize(s));  // tmp2 is released on return
+  // tile counts of every level of the recursion, all scratch in one buffer
+  std::vector<int64_t> lev;
+  for (int64_t m = n; m > 1 || lev.empty();) {
+    const int64_t nt = (m + kScanTile - 1) / kScanTile;
+    lev.push_back(nt);
+    if (nt == 1) break;
+    m = nt;
   }
-  scan_apply<<<(int)ntile, kScanT, 0, s>>>(in, n, offs, out);
+  size_t total = 0;
+  for (int64_t nt : lev) total += 2 * (size_t)nt;
+  tmp.ensure(sizeof(int) * (total + 2));
+  std::vector<int*> sums(lev.size()), offs(lev.size());
+  {
+    int* p = tmp.as<int>();
+    for (size_t l = 0; l < lev.size(); ++l) {
+      sums[l] = p;
+      offs[l] = p + lev[l];
+      p += 2 * lev[l];
+    }
+  }
+  // up: tile sums of each level
+  const int* cur = in;
+  int64_t cur_n = n;
+  for (size_t l = 0; l < lev.size(); ++l) {
+    scan_tile_sums<<<(int)lev[l], kScanT, 0, s>>>(cur, cur_n, sums[l]);
+    QTP_CHECK_LAUNCH();
+    cur = sums[l];
+    cur_n = lev[l];
+  }
+  // down: the top level has one tile, offset 0
+  QTP_HIP(hipMemsetAsync(offs.back(), 0, sizeof(int), s));
+  for (size_t l = lev.size() - 1; l-- > 0;) {
+    scan_apply<<<(int)lev[l + 1], kScanT, 0, s>>>(sums[l], lev[l], offs[l + 1], offs[l]);
+    QTP_CHECK_LAUNCH();
+  }
+  scan_apply<<<(int)lev[0], kScanT, 0, s>>>(in, n, offs[0], out);
   QTP_CHECK_LAUNCH();
 }
 

@@ -266,7 +266,7 @@ double now_ms() {
 }  // namespace
 
 int pdip_solve(Ctx& c, qtp_step_stats* st) {
-  QTP_REQUIRE(c.qp.valid, QTP_E_STATE, "assemble before the PDIP solve");
+  QTP_REQUIRE(c.qp.valid && !c.qp.stale, QTP_E_STATE, "assemble before the PDIP solve");
   const hipStream_t s = c.stream;
   Scene& sc = c.scene;
   Qp& qp = c.qp;

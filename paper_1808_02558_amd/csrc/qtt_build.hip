@@ -295,12 +295,33 @@ void load_from(hipStream_t s, const Qtt& src, DQtt& dst) {
                          sizeof(double) * dst.off[dst.d], hipMemcpyDeviceToDevice, s));
 }
 
-// Scratch shared by the construction steps.
+// Scratch shared by the construction steps.  It lives as long as the
+// context, so the buffers only grow: no allocation (and no hipFree, which
+// synchronises the device) in steady state.
 struct Scratch {
   DevBuf gram, evA, evV, evw, evws, evVs, gemm_ws, t1, t2, t3, partial;
   DevBuf z1, z2, y1, y2;
+  // rounding
+  DevBuf Wb, Wn, Bb, T2, Mm;
+  std::vector<DevBuf> zc;
+  // compression
+  DevBuf W, Pm, Wp;
+  std::vector<DevBuf> cores;
+  // pattern
+  DevBuf brow, tk, tv, th, ts, flag, excl, g;
+  // Newton-Schulz iterates
+  DQtt A, X, AX, Y, XY, T, Xn, bestX;
   Workspace ws() { return Workspace{gemm_ws.get(), gemm_ws.bytes()}; }
 };
+
+__global__ void set_value_kernel(double* __restrict__ p, double v) {
+  if (threadIdx.x == 0) p[0] = v;
+}
+
+void set_value(hipStream_t s, double* p, double v) {
+  set_value_kernel<<<1, 64, 0, s>>>(p, v);
+  QTP_CHECK_LAUNCH();
+}
 
 double host_sum(hipStream_t s, const double* partial, int n) {
   std::vector<double> h(n);
@@ -342,8 +363,7 @@ double tt_round(hipStream_t s, const DQtt& Y, double eps, int rmax, DQtt& Z,
   sc.gram.ensure(sizeof(double) * (size_t)(goff[d] + 1));
   double* G = sc.gram.as<double>();
   auto Gk = [&](int k) { return G + goff[k]; };  // R[k] x R[k]
-  const double one = 1.0;
-  QTP_HIP(hipMemcpyAsync(Gk(d), &one, sizeof(double), hipMemcpyHostToDevice, s));
+  set_value(s, Gk(d), 1.0);
   int64_t maxT = 1;
   for (int k = 1; k <= d; ++k) maxT = std::max<int64_t>(maxT, (int64_t)R[k - 1] * 4 * R[k]);
   sc.t1.ensure(sizeof(double) * maxT);
@@ -365,13 +385,14 @@ double tt_round(hipStream_t s, const DQtt& Y, double eps, int rmax, DQtt& Z,
   const double delta2 = eps * eps * nrm2 / std::max(d - 1, 1);
   // left-to-right truncation
   std::vector<int32_t> rz(d + 1, 1);
-  std::vector<DevBuf> zc(d);
+  if ((int)sc.zc.size() < d) sc.zc.resize(d);
+  std::vector<DevBuf>& zc = sc.zc;
   int64_t maxW = 1;
   for (int k = 0; k <= d; ++k) maxW = std::max<int64_t>(maxW, (int64_t)R[k] * 256);
-  DevBuf Wb, Wn, Bb, T2, Mm;
+  DevBuf &Wb = sc.Wb, &Wn = sc.Wn, &Bb = sc.Bb, &T2 = sc.T2, &Mm = sc.Mm;
   Wb.ensure(sizeof(double) * maxW);
   Wn.ensure(sizeof(double) * maxW);
-  QTP_HIP(hipMemcpyAsync(Wb.get(), &one, sizeof(double), hipMemcpyHostToDevice, s));
+  set_value(s, Wb.as<double>(), 1.0);
   int rp = 1;  // current left rank r'_{k-1}
   for (int k = 1; k <= d; ++k) {
     const double* Yk = Y.core(k - 1);
@@ -416,7 +437,6 @@ double tt_round(hipStream_t s, const DQtt& Y, double eps, int rmax, DQtt& Z,
     QTP_HIP(hipMemcpyAsync(Z.core(k), zc[k].get(),
                            sizeof(double) * (size_t)rz[k] * 4 * rz[k + 1],
                            hipMemcpyDeviceToDevice, s));
-  QTP_HIP(hipStreamSynchronize(s));  // zc buffers are released on return
   return nrm;
 }
 
@@ -477,7 +497,7 @@ struct Builder {
     P.nval = nval;
     P.keys.ensure(sizeof(uint64_t) * nent);
     P.perm.ensure(sizeof(int32_t) * nent);
-    DevBuf brow;
+    DevBuf& brow = sc.brow;
     brow.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(c.nnzb, 1));
     block_rows_kernel<<<div_up(c.nslots, kT), kT, 0, s>>>(c.nslots, c.rp.as<int32_t>(),
                                                          brow.as<int32_t>());
@@ -486,14 +506,14 @@ struct Builder {
         c.nnzb, c.nslots, c.n, brow.as<int32_t>(), c.col.as<int32_t>(),
         P.keys.as<uint64_t>(), P.perm.as<int32_t>());
     QTP_CHECK_LAUNCH();
-    DevBuf tk, tv, th, ts;
+    DevBuf &tk = sc.tk, &tv = sc.tv, &th = sc.th, &ts = sc.ts;
     radix_sort_pairs(s, P.keys.as<uint64_t>(), P.perm.as<int32_t>(), nent, 2 * d,
                      tk, tv, th, ts);
     // level structure: rows of W_k are distinct prefixes z >> 2(d-k+1)
     P.nrows.assign(d + 1, 0);
     P.seg.resize(d + 1);
     P.rowkey.resize(d + 1);
-    DevBuf flag, excl;
+    DevBuf &flag = sc.flag, &excl = sc.excl;
     // leaves (k = d): segments of z >> 2 over the sorted entries
     int64_t cur_n = nent;
     const uint64_t* cur_keys = P.keys.as<uint64_t>();
@@ -535,7 +555,7 @@ struct Builder {
     const int d = c.log2n;
     Workspace ws = sc.ws();
     // leaves
-    DevBuf W, Pm, Wp;
+    DevBuf &W = sc.W, &Pm = sc.Pm, &Wp = sc.Wp;
     W.ensure(sizeof(double) * 4 * P.nrows[d]);
     QTP_HIP(hipMemsetAsync(W.get(), 0, sizeof(double) * 4 * P.nrows[d], s));
     fill_leaves_kernel<<<div_up(P.nent, kT), kT, 0, s>>>(
@@ -550,7 +570,8 @@ struct Builder {
     const double nrm2 = host_sum(s, sc.partial.as<double>(), nb);
     const double delta2 = eps * eps * nrm2 / std::max(d - 1, 1);
     std::vector<int32_t> r(d + 1, 1);
-    std::vector<DevBuf> cores(d);
+    if ((int)sc.cores.size() < d) sc.cores.resize(d);
+    std::vector<DevBuf>& cores = sc.cores;
     int rk = 1;  // r_k of the current level's right part
     for (int k = d; k >= 2; --k) {
       const int cols = 4 * rk;
@@ -595,7 +616,6 @@ struct Builder {
       QTP_HIP(hipMemcpyAsync(A.core(k), cores[k].get(),
                              sizeof(double) * (size_t)r[k] * 4 * r[k + 1],
                              hipMemcpyDeviceToDevice, s));
-    QTP_HIP(hipStreamSynchronize(s));
   }
 
   // probe residual max_z |z - S~ X z| / |z| with the exact scaled matrix
@@ -630,6 +650,13 @@ struct Builder {
 
 }  // namespace
 
+struct BuildCache {
+  Builder b;
+  explicit BuildCache(Ctx& c) : b(c) {}
+};
+
+void destroy_build_cache(BuildCache* bc) { delete bc; }
+
 void build_inverse(Ctx& c, int hot) {
   QTP_REQUIRE(c.have_matrix, QTP_E_STATE, "no Newton matrix loaded");
   const hipStream_t s = c.stream;
@@ -637,46 +664,47 @@ void build_inverse(Ctx& c, int hot) {
   c.sval.ensure(sizeof(double) * 9 * (size_t)c.nnzb);
   bj_scale_matrix(s, c.nslots, c.rp.as<int32_t>(), c.col.as<int32_t>(),
                   c.val.as<double>(), c.Linv.as<double>(), c.sval.as<double>());
-  Builder b(c);
+  if (!c.bcache) c.bcache = new BuildCache(c);
+  Builder& b = c.bcache->b;
+  Scratch& sc = b.sc;
   if (!c.pat.valid || c.pat.d != c.log2n) b.build_pattern();
-  DQtt A;
+  DQtt& A = sc.A;
   b.compress(c.cfg.qtt_eps, c.cfg.qtt_rmax_s, A);
   copy_into(s, A, c.A);
   // Newton-Schulz on S~_TT with probe monitoring on the exact S~
   const int d = c.log2n;
-  DQtt X;
+  DQtt& X = sc.X;
   int iters = c.cfg.ns_iters;
   if (hot && c.have_inverse && c.X.d == d) {
     load_from(s, c.X, X);
     iters = c.cfg.ns_iters_hot;
   } else {
-    DevBuf g;
-    g.ensure(sizeof(double));
+    sc.g.ensure(sizeof(double));
     gershgorin_kernel<<<1, kT, 0, s>>>(c.nslots, c.rp.as<int32_t>(), c.sval.as<double>(),
-                                       g.as<double>());
+                                       sc.g.as<double>());
     QTP_CHECK_LAUNCH();
     double lam = 1.0;
-    QTP_HIP(hipMemcpyAsync(&lam, g.get(), sizeof(double), hipMemcpyDeviceToHost, s));
+    QTP_HIP(hipMemcpyAsync(&lam, sc.g.get(), sizeof(double), hipMemcpyDeviceToHost, s));
     QTP_HIP(hipStreamSynchronize(s));
     scaled_identity(s, d, 1.0 / lam, X);
   }
   double best = b.probe(X);
-  DQtt bestX;
+  DQtt& bestX = sc.bestX;
   bestX.alloc(d, X.r);
   QTP_HIP(hipMemcpyAsync(bestX.buf.get(), X.buf.get(), sizeof(double) * X.off[d],
                          hipMemcpyDeviceToDevice, s));
   c.ns_done = 0;
   for (int it = 0; it < iters; ++it) {
-    DQtt AX, Y, XY, T, Xn;
+    DQtt &AX = sc.AX, &Y = sc.Y, &XY = sc.XY, &T = sc.T, &Xn = sc.Xn;
     tt_matmul(s, A, X, AX);
-    tt_round(s, AX, c.cfg.qtt_eps, c.cfg.qtt_rmax_s, Y, b.sc);
+    tt_round(s, AX, c.cfg.qtt_eps, c.cfg.qtt_rmax_s, Y, sc);
     tt_matmul(s, X, Y, XY);
     tt_axpby(s, 2.0, X, -1.0, XY, T);
-    tt_round(s, T, c.cfg.qtt_eps, c.cfg.qtt_rmax, Xn, b.sc);
+    tt_round(s, T, c.cfg.qtt_eps, c.cfg.qtt_rmax, Xn, sc);
     const double pr = b.probe(Xn);
     X.buf.swap(Xn.buf);
-    X.r = Xn.r;
-    X.off = Xn.off;
+    std::swap(X.r, Xn.r);
+    std::swap(X.off, Xn.off);
     ++c.ns_done;
     if (!(pr < best)) break;  // no progress on the exact matrix: keep the best
     best = pr;
