@@ -75,6 +75,9 @@ def main():
     ap.add_argument("--rmax", type=int, default=32)
     ap.add_argument("--rmax-s", type=int, default=16)
     ap.add_argument("--eps", type=float, default=1e-2)
+    ap.add_argument("--restart", type=int, default=30)
+    ap.add_argument("--ns-iters", type=int, default=6)
+    ap.add_argument("--ns-iters-hot", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--scene", default="hopper")
     a = ap.parse_args()
@@ -95,8 +98,9 @@ def main():
     sc = scenes.make_scene(a.scene)
     ctx = binding.Context(precision=a.precision, qtt_rmax=a.rmax,
                           qtt_rmax_s=a.rmax_s, qtt_eps=a.eps, solve_mode=1,
-                          solve_tol=1e-8, fgmres_restart=30, fgmres_maxit=3000,
-                          ns_iters=6, ns_iters_hot=2)
+                          solve_tol=1e-8, fgmres_restart=a.restart,
+                          fgmres_maxit=3000, ns_iters=a.ns_iters,
+                          ns_iters_hot=a.ns_iters_hot)
 
     def dev(x):
         return torch.from_numpy(np.ascontiguousarray(x)).cuda()
@@ -131,6 +135,9 @@ def main():
     qa_ms, qa_n = ctx.qtp_get_kernel_time("qtt_apply")
     cg_ms, cg_n = ctx.qtp_get_kernel_time("cgs2")
     ctx.qtp_profile(False)
+    ranks_x = ctx.qtp_get_qtt_ranks(1)
+    ranks_s = ctx.qtp_get_qtt_ranks(0)
+    pst = ctx.qtp_get_precond_stats()
     _, _, valN, _ = ctx.qtp_get_qp(sc.log2n)
     nnzb = valN.numel() // 9
     ctx.close()
@@ -158,10 +165,13 @@ def main():
             "workload": f"{a.scene}: {sc.M} spheres, 2^{sc.log2n} unknowns, "
                         f"mu {sc.mu}, h {sc.h}",
             "qtt_cores": a.precision, "qtt_eps": a.eps, "qtt_rmax": a.rmax,
-            "qtt_rmax_s": a.rmax_s, "fgmres": "FGMRES(30) to 1e-8",
+            "qtt_rmax_s": a.rmax_s, "fgmres": f"FGMRES({a.restart}) to 1e-8",
             "pdip_gap_tol": 1e-8,
         },
         "newton_solve_ms": solve_ms,
+        "qtt_ranks_last": {"X": ranks_x, "S": ranks_s,
+                           "ns_iterations": pst.ns_iterations,
+                           "probe_residual": pst.probe_residual},
         "pdip_iterations": [s.pdip_iterations for s in stats],
         "fgmres_iterations_per_newton": fg,
         "contacts": [s.n_contacts for s in stats],

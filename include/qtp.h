@@ -76,8 +76,9 @@ typedef struct {
   double pdip_gap_tol;  /* PDIP stop: gap / m */
   double pdip_dual_tol; /* PDIP stop: |r_dual|_inf in scaled units */
   int pdip_maxit;
-  int warm_start;       /* 0 cold, 1 previous step, 2 learned */
+  int warm_start;       /* 0 cold, 2 learned (MLP) with cold fallback */
   uint64_t seed;
+  double warm_t0;       /* central-path parameter of the learned start */
 } qtp_config;
 
 /* Fills a config with the defaults: FP64, eps 1e-2, rmax 32, rmax_s 16,
@@ -213,6 +214,9 @@ typedef struct {
   double ms_detect, ms_assemble, ms_precond, ms_solve, ms_pdip, ms_integrate;
   double ms_total;
   double newton_solve_ms_median;
+  int warm_started;        /* 1 when the learned start was used */
+  int warm_fallback;       /* 1 when it failed and the cold start ran */
+  int warm_iterations;     /* PDIP iterations spent in the failed warm run */
 } qtp_step_stats;
 
 /* PDIP on the assembled QP (Sec. 2.4 with the Schur-complement Newton system
@@ -234,6 +238,46 @@ qtp_status qtp_get_state(qtp_ctx ctx, double* x, double* v, double* w);
 
 /* detect + assemble + PDIP + integrate. */
 qtp_status qtp_step(qtp_ctx ctx, qtp_step_stats* stats);
+
+/* ---------------------------------------------------------------------------
+ * Learned warm start (an MLP 11 -> 128 -> 128 -> 128 -> 3, FP32, tanh).
+ * The paper starts the PDIP cold (Sec. 3.3, "Re-using information across
+ * timesteps"); with warm_start = 2 the start is the network's prediction,
+ * strictly inside the cone, with multipliers on the central path of warm_t0,
+ * and the cold start runs when that PDIP does not converge.
+ * Parameters are one flat FP32 vector W1 b1 W2 b2 W3 b3 W4 b4 with W_l
+ * stored [fan_in][fan_out] row-major (x W + b).
+ * ------------------------------------------------------------------------- */
+
+/* Number of FP32 parameters (host). */
+int64_t qtp_mlp_param_count(void);
+
+/* Per-contact features of the current contacts [nc][11] FP32 (device);
+ * follows qtp_detect and qtp_assemble. */
+qtp_status qtp_mlp_features(qtp_ctx ctx, float* X);
+
+/* Sets / gets the parameters (device, qtp_mlp_param_count floats); setting
+ * resets the Adam moments. */
+qtp_status qtp_mlp_set_params(qtp_ctx ctx, const float* params);
+qtp_status qtp_mlp_get_params(qtp_ctx ctx, float* params);
+
+/* Fits the feature z-scoring to n rows of X [n][11] (device); the mean and
+ * inverse deviation can be read back (host [11] each). */
+qtp_status qtp_mlp_fit_normalization(qtp_ctx ctx, const float* X, int64_t n);
+qtp_status qtp_mlp_get_normalization(qtp_ctx ctx, float* mean_host,
+                                     float* istd_host);
+
+/* P [B][3] = network(normalised X [B][11]) (device). */
+qtp_status qtp_mlp_forward(qtp_ctx ctx, const float* X, int B, float* P);
+
+/* Loss (mean squared error over rows and outputs) and its gradient with
+ * respect to every parameter (device, qtp_mlp_param_count floats). */
+qtp_status qtp_mlp_loss_grad(qtp_ctx ctx, const float* X, const float* Y, int B,
+                             float* grads, double* loss_host);
+
+/* One Adam step (Kingma & Ba; beta 0.9 / 0.999, eps 1e-8) on a batch. */
+qtp_status qtp_mlp_train_step(qtp_ctx ctx, const float* X, const float* Y,
+                              int B, double lr, double* loss_host);
 
 /* ---------------------------------------------------------------------------
  * Measurement hooks.

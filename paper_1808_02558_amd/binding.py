@@ -45,6 +45,7 @@ class Config(ctypes.Structure):
         ("pdip_maxit", ctypes.c_int),
         ("warm_start", ctypes.c_int),
         ("seed", ctypes.c_uint64),
+        ("warm_t0", ctypes.c_double),
     ]
 
 
@@ -67,7 +68,9 @@ class StepStats(ctypes.Structure):
                 ("ms_assemble", ctypes.c_double), ("ms_precond", ctypes.c_double),
                 ("ms_solve", ctypes.c_double), ("ms_pdip", ctypes.c_double),
                 ("ms_integrate", ctypes.c_double), ("ms_total", ctypes.c_double),
-                ("newton_solve_ms_median", ctypes.c_double)]
+                ("newton_solve_ms_median", ctypes.c_double),
+                ("warm_started", ctypes.c_int), ("warm_fallback", ctypes.c_int),
+                ("warm_iterations", ctypes.c_int)]
 
 
 _lib = None
@@ -102,6 +105,15 @@ SIGNATURES = {
     "qtp_integrate": (_I, [_P]),
     "qtp_get_state": (_I, [_P, _P, _P, _P]),
     "qtp_step": (_I, [_P, _P]),
+    "qtp_mlp_param_count": (_I64, []),
+    "qtp_mlp_features": (_I, [_P, _P]),
+    "qtp_mlp_set_params": (_I, [_P, _P]),
+    "qtp_mlp_get_params": (_I, [_P, _P]),
+    "qtp_mlp_fit_normalization": (_I, [_P, _P, _I64]),
+    "qtp_mlp_get_normalization": (_I, [_P, _P, _P]),
+    "qtp_mlp_forward": (_I, [_P, _P, _I, _P]),
+    "qtp_mlp_loss_grad": (_I, [_P, _P, _P, _I, _P, _P]),
+    "qtp_mlp_train_step": (_I, [_P, _P, _P, _I, ctypes.c_double, _P]),
     "qtp_profile": (_I, [_P, _I]),
     "qtp_get_kernel_time": (_I, [_P, ctypes.c_char_p, _P, _P]),
     "qtp_get_qtt_ranks": (_I, [_P, _I, _P]),
@@ -299,6 +311,56 @@ class Context:
         st = StepStats()
         rc = self._check(self.lib.qtp_step(self.h, ctypes.byref(st)), allow_nc=True)
         return rc, st
+
+    # ---- learned warm start ------------------------------------------------
+    def qtp_mlp_param_count(self):
+        return int(self.lib.qtp_mlp_param_count())
+
+    def qtp_mlp_features(self, nc):
+        import torch
+        X = torch.empty(nc, 11, dtype=torch.float32, device="cuda")
+        self._check(self.lib.qtp_mlp_features(self.h, _ptr(X)))
+        return X
+
+    def qtp_mlp_set_params(self, params):
+        return self._check(self.lib.qtp_mlp_set_params(self.h, _ptr(params)))
+
+    def qtp_mlp_get_params(self):
+        import torch
+        p = torch.empty(self.qtp_mlp_param_count(), dtype=torch.float32, device="cuda")
+        self._check(self.lib.qtp_mlp_get_params(self.h, _ptr(p)))
+        return p
+
+    def qtp_mlp_fit_normalization(self, X):
+        return self._check(self.lib.qtp_mlp_fit_normalization(
+            self.h, _ptr(X), int(X.shape[0])))
+
+    def qtp_mlp_get_normalization(self):
+        mean = (ctypes.c_float * 11)()
+        istd = (ctypes.c_float * 11)()
+        self._check(self.lib.qtp_mlp_get_normalization(self.h, mean, istd))
+        return list(mean), list(istd)
+
+    def qtp_mlp_forward(self, X):
+        import torch
+        P = torch.empty(X.shape[0], 3, dtype=torch.float32, device="cuda")
+        self._check(self.lib.qtp_mlp_forward(self.h, _ptr(X), int(X.shape[0]), _ptr(P)))
+        return P
+
+    def qtp_mlp_loss_grad(self, X, Y):
+        import torch
+        g = torch.empty(self.qtp_mlp_param_count(), dtype=torch.float32, device="cuda")
+        loss = ctypes.c_double()
+        self._check(self.lib.qtp_mlp_loss_grad(self.h, _ptr(X), _ptr(Y), int(X.shape[0]),
+                                               _ptr(g), ctypes.byref(loss)))
+        return loss.value, g
+
+    def qtp_mlp_train_step(self, X, Y, lr=1e-3):
+        loss = ctypes.c_double()
+        self._check(self.lib.qtp_mlp_train_step(self.h, _ptr(X), _ptr(Y),
+                                                int(X.shape[0]), float(lr),
+                                                ctypes.byref(loss)))
+        return loss.value
 
     def qtp_profile(self, enable=True):
         return self._check(self.lib.qtp_profile(self.h, int(bool(enable))))

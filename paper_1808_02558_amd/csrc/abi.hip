@@ -100,6 +100,7 @@ void qtp_config_default(qtp_config* cfg) {
   cfg->pdip_maxit = 100;
   cfg->warm_start = 0;
   cfg->seed = 0;
+  cfg->warm_t0 = 100.0;
 }
 
 qtp_status qtp_create(const qtp_config* cfg, void* hip_stream, qtp_ctx* out) {
@@ -484,6 +485,87 @@ qtp_status qtp_step(qtp_ctx ctx, qtp_step_stats* stats) {
     st->ms_integrate = ms(t3, t4);
     st->ms_total = ms(t0, t4);
     return rc;
+  });
+}
+
+int64_t qtp_mlp_param_count(void) { return qtp::mlp_param_count(); }
+
+qtp_status qtp_mlp_features(qtp_ctx ctx, float* X) {
+  return guarded(ctx, [&](Ctx& c) {
+    QTP_REQUIRE(X, QTP_E_ARG, "null pointer");
+    qtp::mlp_features(c, X);
+    return QTP_OK;
+  });
+}
+
+qtp_status qtp_mlp_set_params(qtp_ctx ctx, const float* params) {
+  return guarded(ctx, [&](Ctx& c) {
+    QTP_REQUIRE(params, QTP_E_ARG, "null pointer");
+    qtp::mlp_set_params(c, params);
+    return QTP_OK;
+  });
+}
+
+qtp_status qtp_mlp_get_params(qtp_ctx ctx, float* params) {
+  return guarded(ctx, [&](Ctx& c) {
+    QTP_REQUIRE(params, QTP_E_ARG, "null pointer");
+    QTP_REQUIRE(c.mlp.have_params, QTP_E_STATE, "MLP parameters not set");
+    QTP_HIP(hipMemcpyAsync(params, c.mlp.params.get(),
+                           sizeof(float) * qtp::mlp_param_count(),
+                           hipMemcpyDeviceToDevice, c.stream));
+    QTP_HIP(hipStreamSynchronize(c.stream));
+    return QTP_OK;
+  });
+}
+
+qtp_status qtp_mlp_fit_normalization(qtp_ctx ctx, const float* X, int64_t n) {
+  return guarded(ctx, [&](Ctx& c) {
+    QTP_REQUIRE(X, QTP_E_ARG, "null pointer");
+    qtp::mlp_fit_normalisation(c, X, n);
+    return QTP_OK;
+  });
+}
+
+qtp_status qtp_mlp_get_normalization(qtp_ctx ctx, float* mean_host, float* istd_host) {
+  return guarded(ctx, [&](Ctx& c) {
+    QTP_REQUIRE(mean_host && istd_host, QTP_E_ARG, "null pointer");
+    qtp::mlp_get_normalisation(c, mean_host, istd_host);
+    return QTP_OK;
+  });
+}
+
+qtp_status qtp_mlp_forward(qtp_ctx ctx, const float* X, int B, float* P) {
+  return guarded(ctx, [&](Ctx& c) {
+    QTP_REQUIRE(X && P && B >= 1, QTP_E_ARG, "bad arguments");
+    qtp::mlp_forward(c, X, B, P);
+    QTP_HIP(hipStreamSynchronize(c.stream));
+    return QTP_OK;
+  });
+}
+
+qtp_status qtp_mlp_loss_grad(qtp_ctx ctx, const float* X, const float* Y, int B,
+                             float* grads, double* loss_host) {
+  return guarded(ctx, [&](Ctx& c) {
+    QTP_REQUIRE(X && Y && B >= 1, QTP_E_ARG, "bad arguments");
+    const double loss = qtp::mlp_loss_grad(c, X, Y, B);
+    if (loss_host) *loss_host = loss;
+    if (grads) {
+      QTP_HIP(hipMemcpyAsync(grads, c.mlp.grads.get(),
+                             sizeof(float) * qtp::mlp_param_count(),
+                             hipMemcpyDeviceToDevice, c.stream));
+      QTP_HIP(hipStreamSynchronize(c.stream));
+    }
+    return QTP_OK;
+  });
+}
+
+qtp_status qtp_mlp_train_step(qtp_ctx ctx, const float* X, const float* Y, int B,
+                              double lr, double* loss_host) {
+  return guarded(ctx, [&](Ctx& c) {
+    QTP_REQUIRE(X && Y && B >= 1 && lr > 0.0, QTP_E_ARG, "bad arguments");
+    const double loss = qtp::mlp_train_step(c, X, Y, B, lr);
+    if (loss_host) *loss_host = loss;
+    return QTP_OK;
   });
 }
 

@@ -3,6 +3,8 @@
 // Reductions are deterministic: every block writes one partial sum per
 // output in a fixed order, and a second single-block pass adds the partials
 // in index order.  No floating-point atomics.
+#include <algorithm>
+
 #include "ops.h"
 
 namespace qtp {
@@ -27,57 +29,78 @@ __device__ inline double block_sum(double v, double* sh) {
   return s;  // valid in thread 0
 }
 
-// partial[blk * nvec + l] = sum over this block's chunk of V_l[i] * w[i]
-__global__ __launch_bounds__(kThreads) void multi_dot_kernel(
-    int nvec, const double* __restrict__ V, int64_t ldv,
-    const double* __restrict__ w, int64_t n, double* __restrict__ partial) {
-  __shared__ double sh[kThreads / 64];
-  const int64_t stride = (int64_t)gridDim.x * kThreads;
-  for (int l = 0; l < nvec; ++l) {
-    double acc = 0.0;
-    const double* v = V + (int64_t)l * ldv;
-    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
-         i += stride)
-      acc += v[i] * w[i];
-    const double s = block_sum(acc, sh);
-    if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * nvec + l] = s;
-  }
-}
-
-// w -= sum_l h_l V_l (in place), then partial dots of V_l with the new w
-// (mode 0) or the partial of |w|^2 (mode 1).
-template <int MODE>
-__global__ __launch_bounds__(kThreads) void cgs_update_kernel(
+// One pass over up to NV basis vectors V_l (register blocked: each V_l[i] is
+// loaded once and kept in a register for both of its uses).
+//   MODE 0: partial dots V_l . w
+//   MODE 1: w -= sum_l h_l V_l, then partial dots V_l . w (new w)
+//   MODE 2: w -= sum_l h_l V_l, then the partial of |w|^2
+//   MODE 3: w -= sum_l h_l V_l only
+// Partials go to partial[blk * pstride + poff + l].
+template <int NV, int MODE>
+__global__ __launch_bounds__(kThreads) void cgs_kernel(
     int nvec, const double* __restrict__ V, int64_t ldv,
     const double* __restrict__ h, double* __restrict__ w, int64_t n,
-    double* __restrict__ partial) {
-  __shared__ double sh[kThreads / 64];
-  __shared__ double hs[kMaxVec];
-  if (threadIdx.x < nvec) hs[threadIdx.x] = h[threadIdx.x];
-  __syncthreads();
-  const int64_t stride = (int64_t)gridDim.x * kThreads;
-  double acc[MODE == 0 ? kMaxVec : 1];
-  if (MODE == 0) {
-    for (int l = 0; l < nvec; ++l) acc[l] = 0.0;
-  } else {
-    acc[0] = 0.0;
+    double* __restrict__ partial, int pstride, int poff) {
+  constexpr int NACC = MODE == 0 || MODE == 1 ? NV : 1;
+  __shared__ double hs[NV];
+  __shared__ double red[NACC][kThreads / 64];
+  if (MODE != 0) {
+    if (threadIdx.x < NV) hs[threadIdx.x] = threadIdx.x < nvec ? h[threadIdx.x] : 0.0;
+    __syncthreads();
   }
-  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
-       i += stride) {
+  double acc[NACC];
+#pragma unroll
+  for (int l = 0; l < NACC; ++l) acc[l] = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * kThreads;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += stride) {
+    double v[NV];
+#pragma unroll
+    for (int l = 0; l < NV; ++l) v[l] = l < nvec ? V[(int64_t)l * ldv + i] : 0.0;
     double wi = w[i];
-    for (int l = 0; l < nvec; ++l) wi -= hs[l] * V[(int64_t)l * ldv + i];
-    w[i] = wi;
-    if (MODE == 0) {
-      for (int l = 0; l < nvec; ++l) acc[l] += V[(int64_t)l * ldv + i] * wi;
-    } else {
+    if (MODE != 0) {
+#pragma unroll
+      for (int l = 0; l < NV; ++l) wi -= hs[l] * v[l];
+      w[i] = wi;
+    }
+    if (MODE == 0 || MODE == 1) {
+#pragma unroll
+      for (int l = 0; l < NV; ++l) acc[l] += v[l] * wi;
+    } else if (MODE == 2) {
       acc[0] += wi * wi;
     }
   }
-  const int nout = MODE == 0 ? nvec : 1;
-  for (int l = 0; l < nout; ++l) {
-    const double s = block_sum(acc[l], sh);
-    if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * nout + l] = s;
+  if (MODE == 3) return;
+  const int nout = MODE == 2 ? 1 : nvec;
+  const int wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int l = 0; l < NACC; ++l) {
+    double s = acc[l];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if ((threadIdx.x & 63) == 0) red[l][wave] = s;
   }
+  __syncthreads();
+  if (threadIdx.x < nout) {
+    double s = 0.0;
+    for (int q = 0; q < kThreads / 64; ++q) s += red[threadIdx.x][q];
+    partial[(int64_t)blockIdx.x * pstride + poff + threadIdx.x] = s;
+  }
+}
+
+template <int MODE>
+void launch_cgs(hipStream_t s, int nb, int nvec, const double* V, int64_t ldv,
+                const double* h, double* w, int64_t n, double* partial, int pstride,
+                int poff) {
+  if (nvec <= 8)
+    cgs_kernel<8, MODE><<<nb, kThreads, 0, s>>>(nvec, V, ldv, h, w, n, partial,
+                                                pstride, poff);
+  else if (nvec <= 16)
+    cgs_kernel<16, MODE><<<nb, kThreads, 0, s>>>(nvec, V, ldv, h, w, n, partial,
+                                                 pstride, poff);
+  else
+    cgs_kernel<32, MODE><<<nb, kThreads, 0, s>>>(nvec, V, ldv, h, w, n, partial,
+                                                 pstride, poff);
+  QTP_CHECK_LAUNCH();
 }
 
 // out[l] = sum_b partial[b * nvec + l], fixed order
@@ -262,8 +285,9 @@ void multi_dot(hipStream_t s, int nvec, const double* V, int64_t ldv,
                const double* w, int64_t n, double* partial, double* out) {
   QTP_REQUIRE(nvec >= 1 && nvec <= kMaxVec, -1, "multi_dot: nvec out of range");
   const int nb = grid_for(n);
-  multi_dot_kernel<<<nb, kThreads, 0, s>>>(nvec, V, ldv, w, n, partial);
-  QTP_CHECK_LAUNCH();
+  for (int c0 = 0; c0 < nvec; c0 += 32)
+    launch_cgs<0>(s, nb, std::min(32, nvec - c0), V + (int64_t)c0 * ldv, ldv,
+                  nullptr, const_cast<double*>(w), n, partial, nvec, c0);
   finish_kernel<<<1, kThreads, 0, s>>>(nb, nvec, partial, out);
   QTP_CHECK_LAUNCH();
 }
@@ -273,10 +297,16 @@ void cgs_update_dot(hipStream_t s, int nvec, const double* V, int64_t ldv,
                     double* out) {
   QTP_REQUIRE(nvec >= 1 && nvec <= kMaxVec, -1, "cgs_update_dot: nvec out of range");
   const int nb = grid_for(n);
-  cgs_update_kernel<0><<<nb, kThreads, 0, s>>>(nvec, V, ldv, h, w, n, partial);
-  QTP_CHECK_LAUNCH();
-  finish_kernel<<<1, kThreads, 0, s>>>(nb, nvec, partial, out);
-  QTP_CHECK_LAUNCH();
+  if (nvec <= 32) {
+    launch_cgs<1>(s, nb, nvec, V, ldv, h, w, n, partial, nvec, 0);
+    finish_kernel<<<1, kThreads, 0, s>>>(nb, nvec, partial, out);
+    QTP_CHECK_LAUNCH();
+    return;
+  }
+  for (int c0 = 0; c0 < nvec; c0 += 32)
+    launch_cgs<3>(s, nb, std::min(32, nvec - c0), V + (int64_t)c0 * ldv, ldv,
+                  h + c0, w, n, partial, 0, 0);
+  multi_dot(s, nvec, V, ldv, w, n, partial, out);
 }
 
 void cgs_update_norm2(hipStream_t s, int nvec, const double* V, int64_t ldv,
@@ -284,8 +314,11 @@ void cgs_update_norm2(hipStream_t s, int nvec, const double* V, int64_t ldv,
                       double* out) {
   QTP_REQUIRE(nvec >= 1 && nvec <= kMaxVec, -1, "cgs_update_norm2: nvec out of range");
   const int nb = grid_for(n);
-  cgs_update_kernel<1><<<nb, kThreads, 0, s>>>(nvec, V, ldv, h, w, n, partial);
-  QTP_CHECK_LAUNCH();
+  int c0 = 0;
+  for (; nvec - c0 > 32; c0 += 32)
+    launch_cgs<3>(s, nb, 32, V + (int64_t)c0 * ldv, ldv, h + c0, w, n, partial, 0, 0);
+  launch_cgs<2>(s, nb, nvec - c0, V + (int64_t)c0 * ldv, ldv, h + c0, w, n, partial,
+                1, 0);
   finish_kernel<<<1, kThreads, 0, s>>>(nb, 1, partial, out);
   QTP_CHECK_LAUNCH();
 }

@@ -5,6 +5,7 @@
 
 #include "../../include/qtp.h"
 #include "common.h"
+#include "mlp.h"
 #include "ops.h"
 
 namespace qtp {
@@ -97,6 +98,7 @@ struct Ctx {
   Contacts ct;
   Qp qp;
   Pdip pd;
+  Mlp mlp;
   // temporaries of detection and assembly
   DevBuf tmp1, cnt, offs, cnt2, offs2, ua, ub, pk, perm, perm2;
   DevBuf sk, sv, sh, ss;  // sort and scan scratch

@@ -265,7 +265,7 @@ double now_ms() {
 
 }  // namespace
 
-int pdip_solve(Ctx& c, qtp_step_stats* st) {
+static int pdip_run(Ctx& c, qtp_step_stats* st, bool warm) {
   QTP_REQUIRE(c.qp.valid && !c.qp.stale, QTP_E_STATE, "assemble before the PDIP solve");
   const hipStream_t s = c.stream;
   Scene& sc = c.scene;
@@ -335,8 +335,12 @@ int pdip_solve(Ctx& c, qtp_step_stats* st) {
     st->ms_pdip = 0.0;
     return QTP_OK;
   }
-  init_kernel<<<div_up(nc, kT), kT, 0, s>>>(nc, mu, slot, gamma, lam);
-  QTP_CHECK_LAUNCH();
+  if (warm) {
+    mlp_warm_start(c, c.cfg.warm_t0, gamma, lam);
+  } else {
+    init_kernel<<<div_up(nc, kT), kT, 0, s>>>(nc, mu, slot, gamma, lam);
+    QTP_CHECK_LAUNCH();
+  }
   const double m = 2.0 * nc;
   int it = 0;
   double gap = 0.0, rdinf = 0.0;
@@ -459,6 +463,35 @@ __global__ void gather_impulses_kernel(int nc, double gbar,
   for (int c = 0; c < 3; ++c) out[3 * (int64_t)i + c] = gbar * gamma[q + c];
 }
 }  // namespace
+
+// The learned start when configured and trained, with the cold start of
+// Sec. 3.3 as the fallback when that run fails or does not converge.
+int pdip_solve(Ctx& c, qtp_step_stats* st) {
+  st->warm_started = 0;
+  st->warm_fallback = 0;
+  st->warm_iterations = 0;
+  if (c.cfg.warm_start == 2 && c.mlp.have_params && c.ct.nc > 0) {
+    st->warm_started = 1;
+    int rc = QTP_NOT_CONVERGED;
+    try {
+      rc = pdip_run(c, st, true);
+    } catch (const Error& e) {
+      if (e.status != QTP_E_NUMERIC) throw;
+    }
+    if (rc == QTP_OK) return rc;
+    const int wit = st->pdip_iterations;
+    const double wpre = st->ms_precond, wsol = st->ms_solve;
+    const int wfg = st->fgmres_iterations;
+    rc = pdip_run(c, st, false);
+    st->warm_fallback = 1;
+    st->warm_iterations = wit;
+    st->ms_precond += wpre;
+    st->ms_solve += wsol;
+    st->fgmres_iterations += wfg;
+    return rc;
+  }
+  return pdip_run(c, st, false);
+}
 
 void gather_impulses(Ctx& c, double* out) {
   QTP_REQUIRE(c.pd.have_gamma, QTP_E_STATE, "no PDIP solution");

@@ -29,3 +29,14 @@ def random_qtt_cores(ranks, seed, scale=None):
 
 def random_vector(n, seed):
     return np.random.default_rng(seed).standard_normal(n)
+
+
+def mlp_init(layers, seed):
+    """Initial MLP parameters [W1, b1, W2, b2, ...], W ~ U(+-sqrt(6/(fan_in+fan_out)))."""
+    rng = np.random.default_rng(seed)
+    params = []
+    for fin, fout in zip(layers[:-1], layers[1:]):
+        lim = np.sqrt(6.0 / (fin + fout))
+        params.append(rng.uniform(-lim, lim, size=(fin, fout)))
+        params.append(np.zeros(fout))
+    return params
