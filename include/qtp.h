@@ -79,6 +79,10 @@ typedef struct {
   int warm_start;       /* 0 cold, 2 learned (MLP) with cold fallback */
   uint64_t seed;
   double warm_t0;       /* central-path parameter of the learned start */
+  int qtt_mode;         /* PDIP preconditioner: 0 block-Jacobi only (X = I),
+                           1 QTT inverse on every Newton step,
+                           2 auto: the first Newton step of a time step is
+                             solved with both, the faster is kept */
 } qtp_config;
 
 /* Fills a config with the defaults: FP64, eps 1e-2, rmax 32, rmax_s 16,
@@ -214,6 +218,9 @@ typedef struct {
   double ms_detect, ms_assemble, ms_precond, ms_solve, ms_pdip, ms_integrate;
   double ms_total;
   double newton_solve_ms_median;
+  int qtt_used;            /* Newton steps solved with the QTT inverse */
+  int qtt_trial_iterations;   /* auto mode: FGMRES its of the QTT trial */
+  int plain_trial_iterations; /* auto mode: FGMRES its of the X = I trial */
   int warm_started;        /* 1 when the learned start was used */
   int warm_fallback;       /* 1 when it failed and the cold start ran */
   int warm_iterations;     /* PDIP iterations spent in the failed warm run */

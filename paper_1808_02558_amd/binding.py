@@ -46,6 +46,7 @@ class Config(ctypes.Structure):
         ("warm_start", ctypes.c_int),
         ("seed", ctypes.c_uint64),
         ("warm_t0", ctypes.c_double),
+        ("qtt_mode", ctypes.c_int),
     ]
 
 
@@ -69,6 +70,8 @@ class StepStats(ctypes.Structure):
                 ("ms_solve", ctypes.c_double), ("ms_pdip", ctypes.c_double),
                 ("ms_integrate", ctypes.c_double), ("ms_total", ctypes.c_double),
                 ("newton_solve_ms_median", ctypes.c_double),
+                ("qtt_used", ctypes.c_int), ("qtt_trial_iterations", ctypes.c_int),
+                ("plain_trial_iterations", ctypes.c_int),
                 ("warm_started", ctypes.c_int), ("warm_fallback", ctypes.c_int),
                 ("warm_iterations", ctypes.c_int)]
 

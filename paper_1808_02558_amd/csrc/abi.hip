@@ -78,6 +78,9 @@ void qtp::Ctx::check_cfg() {
   QTP_REQUIRE(cfg.solve_tol > 0.0, QTP_E_ARG, "solve_tol <= 0");
   QTP_REQUIRE(cfg.solve_mode == 0 || cfg.solve_mode == 1, QTP_E_ARG, "bad solve_mode");
   QTP_REQUIRE(cfg.ns_iters >= 0 && cfg.ns_iters_hot >= 0, QTP_E_ARG, "ns_iters < 0");
+  QTP_REQUIRE(cfg.qtt_mode >= 0 && cfg.qtt_mode <= 2, QTP_E_ARG, "qtt_mode out of [0,2]");
+  QTP_REQUIRE(cfg.warm_start == 0 || cfg.warm_start == 2, QTP_E_ARG,
+              "warm_start must be 0 or 2");
 }
 
 extern "C" {
@@ -101,6 +104,7 @@ void qtp_config_default(qtp_config* cfg) {
   cfg->warm_start = 0;
   cfg->seed = 0;
   cfg->warm_t0 = 100.0;
+  cfg->qtt_mode = 2;
 }
 
 qtp_status qtp_create(const qtp_config* cfg, void* hip_stream, qtp_ctx* out) {
@@ -234,6 +238,7 @@ qtp_status qtp_precond_build(qtp_ctx ctx, int hot) {
     qtp::precond_factor(c);
     c.have_precond = true;
     qtp::build_inverse(c, hot);
+    c.use_qtt = true;
     QTP_HIP(hipEventRecord(e1, c.stream));
     QTP_HIP(hipEventSynchronize(e1));
     float ms = 0.f;
@@ -280,6 +285,7 @@ qtp_status qtp_precond_load_qtt(qtp_ctx ctx, int d, const int32_t* ranks,
                            hipMemcpyDeviceToDevice, c.stream));
     c.X.lp_prec = 0;
     c.have_inverse = true;
+    c.use_qtt = true;
     QTP_HIP(hipStreamSynchronize(c.stream));
     return QTP_OK;
   });

@@ -103,17 +103,21 @@ void launch_cgs(hipStream_t s, int nb, int nvec, const double* V, int64_t ldv,
   QTP_CHECK_LAUNCH();
 }
 
-// out[l] = sum_b partial[b * nvec + l], fixed order
+// out[l] = sum_b partial[b * nvec + l] in a fixed order; one wavefront per
+// output l (grid = nvec, 64 threads).
 __global__ void finish_kernel(int nblk, int nvec, const double* __restrict__ partial,
                               double* __restrict__ out) {
-  __shared__ double sh[kThreads / 64];
-  for (int l = 0; l < nvec; ++l) {
-    double acc = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += kThreads)
-      acc += partial[(int64_t)b * nvec + l];
-    const double s = block_sum(acc, sh);
-    if (threadIdx.x == 0) out[l] = s;
-  }
+  const int l = blockIdx.x;
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += 64) acc += partial[(int64_t)b * nvec + l];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if (threadIdx.x == 0) out[l] = acc;
+}
+
+void finish(hipStream_t s, int nblk, int nvec, const double* partial, double* out) {
+  finish_kernel<<<nvec, 64, 0, s>>>(nblk, nvec, partial, out);
+  QTP_CHECK_LAUNCH();
 }
 
 __global__ void scale_kernel(const double* __restrict__ a, int inv,
@@ -288,8 +292,7 @@ void multi_dot(hipStream_t s, int nvec, const double* V, int64_t ldv,
   for (int c0 = 0; c0 < nvec; c0 += 32)
     launch_cgs<0>(s, nb, std::min(32, nvec - c0), V + (int64_t)c0 * ldv, ldv,
                   nullptr, const_cast<double*>(w), n, partial, nvec, c0);
-  finish_kernel<<<1, kThreads, 0, s>>>(nb, nvec, partial, out);
-  QTP_CHECK_LAUNCH();
+  finish(s, nb, nvec, partial, out);
 }
 
 void cgs_update_dot(hipStream_t s, int nvec, const double* V, int64_t ldv,
@@ -299,8 +302,7 @@ void cgs_update_dot(hipStream_t s, int nvec, const double* V, int64_t ldv,
   const int nb = grid_for(n);
   if (nvec <= 32) {
     launch_cgs<1>(s, nb, nvec, V, ldv, h, w, n, partial, nvec, 0);
-    finish_kernel<<<1, kThreads, 0, s>>>(nb, nvec, partial, out);
-    QTP_CHECK_LAUNCH();
+    finish(s, nb, nvec, partial, out);
     return;
   }
   for (int c0 = 0; c0 < nvec; c0 += 32)
@@ -319,8 +321,7 @@ void cgs_update_norm2(hipStream_t s, int nvec, const double* V, int64_t ldv,
     launch_cgs<3>(s, nb, 32, V + (int64_t)c0 * ldv, ldv, h + c0, w, n, partial, 0, 0);
   launch_cgs<2>(s, nb, nvec - c0, V + (int64_t)c0 * ldv, ldv, h + c0, w, n, partial,
                 1, 0);
-  finish_kernel<<<1, kThreads, 0, s>>>(nb, 1, partial, out);
-  QTP_CHECK_LAUNCH();
+  finish(s, nb, 1, partial, out);
 }
 
 void dot(hipStream_t s, const double* x, const double* y, int64_t n,

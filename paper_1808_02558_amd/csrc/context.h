@@ -68,6 +68,7 @@ struct Qp {
 // PDIP iterate and work vectors.
 struct Pdip {
   DevBuf gamma, dgamma, u, wv, rhs;   // padded [n]
+  DevBuf dtrial;                       // second Newton step of the auto trial
   DevBuf lam, dlam;                    // [2 nc]: cone part then gamma_n part
   DevBuf part;                         // reduction partials
   bool have_gamma = false;
@@ -118,6 +119,8 @@ struct Ctx {
   Qtt X;              // approximate inverse
   bool have_precond = false;
   bool have_inverse = false;
+  bool use_qtt = true;          // apply X (else the block-Jacobi part only)
+  bool auto_qtt = false;        // auto mode's choice for the current time step
   Pattern pat;
   int ns_done = 0;              // Newton-Schulz iterations of the last build
   double probe_residual = 0.0;  // rms of z - S~ X z over the probes

@@ -325,6 +325,10 @@ static int pdip_run(Ctx& c, qtp_step_stats* st, bool warm) {
   st->max_fgmres = 0;
   st->ms_precond = 0.0;
   st->ms_solve = 0.0;
+  st->qtt_used = 0;
+  st->qtt_trial_iterations = 0;
+  st->plain_trial_iterations = 0;
+  c.auto_qtt = false;
   std::vector<double> solve_ms;
   const double t_begin = now_ms();
   if (nc == 0) {
@@ -384,17 +388,62 @@ static int pdip_run(Ctx& c, qtp_step_stats* st, bool warm) {
     double t0 = now_ms();
     precond_factor(c);
     c.have_precond = true;
-    build_inverse(c, (it > 0 || c.have_inverse) ? 1 : 0);
     st->ms_precond += now_ms() - t0;
+    const int mode = c.cfg.qtt_mode;
     qtp_solve_stats ss{};
-    t0 = now_ms();
-    const int src = newton_solve(c, pd.rhs.as<double>(), dgamma, &ss);
-    const double sms = now_ms() - t0;
-    st->ms_solve += sms;
+    int src;
+    double sms;
+    if (mode == 2 && it == 0) {
+      // auto: solve the first Newton step with X = I and with the QTT inverse,
+      // keep the faster for the rest of the time step
+      c.use_qtt = false;
+      t0 = now_ms();
+      src = newton_solve(c, pd.rhs.as<double>(), dgamma, &ss);
+      const double ms_i = now_ms() - t0;
+      if (src != QTP_OK) throw Error(QTP_E_NUMERIC, "Newton-step solve did not converge");
+      st->plain_trial_iterations = ss.iterations;
+      t0 = now_ms();
+      build_inverse(c, c.have_inverse ? 1 : 0);
+      c.use_qtt = true;
+      const double ms_b = now_ms() - t0;
+      st->ms_precond += ms_b;
+      pd.dtrial.ensure(sizeof(double) * n);
+      qtp_solve_stats s2{};
+      t0 = now_ms();
+      const int src2 = newton_solve(c, pd.rhs.as<double>(), pd.dtrial.as<double>(), &s2);
+      const double ms_x = now_ms() - t0;
+      st->qtt_trial_iterations = s2.iterations;
+      st->ms_solve += ms_i + ms_x;
+      st->fgmres_iterations += ss.iterations + s2.iterations;
+      c.auto_qtt = src2 == QTP_OK && ms_b + ms_x < ms_i;
+      c.use_qtt = c.auto_qtt;
+      if (c.auto_qtt) {
+        QTP_HIP(hipMemcpyAsync(dgamma, pd.dtrial.get(), sizeof(double) * n,
+                               hipMemcpyDeviceToDevice, s));
+        ss = s2;
+        sms = ms_x;
+        st->qtt_used += 1;
+      } else {
+        sms = ms_i;
+      }
+    } else {
+      const bool q = mode == 1 || (mode == 2 && c.auto_qtt);
+      if (q) {
+        t0 = now_ms();
+        build_inverse(c, (it > 0 || c.have_inverse) ? 1 : 0);
+        st->ms_precond += now_ms() - t0;
+        st->qtt_used += 1;
+      }
+      c.use_qtt = q;
+      t0 = now_ms();
+      src = newton_solve(c, pd.rhs.as<double>(), dgamma, &ss);
+      sms = now_ms() - t0;
+      st->ms_solve += sms;
+      st->fgmres_iterations += ss.iterations;
+      if (src != QTP_OK) throw Error(QTP_E_NUMERIC, "Newton-step solve did not converge");
+    }
     solve_ms.push_back(sms);
-    st->fgmres_iterations += ss.iterations;
     st->max_fgmres = std::max(st->max_fgmres, ss.iterations);
-    if (src != QTP_OK) throw Error(QTP_E_NUMERIC, "Newton-step solve did not converge");
     // Delta lambda and the step bound
     dlam_kernel<<<nb, kT, 0, s>>>(nc, mu, t, slot, gamma, dgamma, lam, dlam, part);
     QTP_CHECK_LAUNCH();

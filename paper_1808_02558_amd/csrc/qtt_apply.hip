@@ -219,7 +219,9 @@ void apply_fused(hipStream_t s, int d, const int32_t* ranks, const CT* cores,
       log2T = std::min(4, log2J);
       int rm = 1;
       for (int l = 0; l <= m; ++l) rm = std::max<int>(rm, ranks[k0 - 1 + l]);
-      if (((size_t)rm << (m + log2T)) <= budget) break;
+      // enough workgroups to fill the 256 CUs (unless no shorter pass helps)
+      const int64_t nblk = ((int64_t)1 << (k0 - 1)) << (log2J - log2T);
+      if (((size_t)rm << (m + log2T)) <= budget && (nblk >= 1024 || m == 1)) break;
     }
     QTP_REQUIRE(m >= 1, -1, "QTT rank too large for the fused apply");
     FusePlan P{};

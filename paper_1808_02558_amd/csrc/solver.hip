@@ -240,7 +240,7 @@ void precond_apply(Ctx& c, const double* v, double* z) {
   double* t1 = c.t1.as<double>();
   double* t2 = c.t2.as<double>();
   bj_apply(c.stream, c.nslots, c.n, c.Linv.as<double>(), 0, v, t1);
-  if (c.have_inverse) {
+  if (c.have_inverse && c.use_qtt) {
     Qtt& X = c.X;
     const void* cores = X.cores.get();
     if (c.cfg.precision != 0) {
