@@ -80,6 +80,8 @@ def main():
     ap.add_argument("--ns-iters-hot", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--scene", default="hopper")
+    ap.add_argument("--qtt-mode", type=int, default=2, choices=[0, 1, 2],
+                    help="0 block-Jacobi only, 1 QTT inverse always, 2 per-step trial")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {a.gpus}); the "
@@ -100,7 +102,7 @@ def main():
                           qtt_rmax_s=a.rmax_s, qtt_eps=a.eps, solve_mode=1,
                           solve_tol=1e-8, fgmres_restart=a.restart,
                           fgmres_maxit=3000, ns_iters=a.ns_iters,
-                          ns_iters_hot=a.ns_iters_hot)
+                          ns_iters_hot=a.ns_iters_hot, qtt_mode=a.qtt_mode)
 
     def dev(x):
         return torch.from_numpy(np.ascontiguousarray(x)).cuda()
@@ -111,6 +113,7 @@ def main():
     n = 1 << sc.log2n
 
     stats = []
+    recs = []
     for i in range(a.warmup):
         rc, st = ctx.qtp_step()
         print(f"warmup step {i}: {st.n_contacts} contacts, {st.pdip_iterations} PDIP "
@@ -122,9 +125,10 @@ def main():
     for i in range(a.steps):
         rc, st = ctx.qtp_step()
         stats.append(st)
+        recs.extend(ctx.qtp_get_newton_log())
         print(f"step {i}: {st.n_contacts} contacts, {st.pdip_iterations} PDIP its "
               f"(converged {st.converged}), {st.fgmres_iterations} FGMRES its "
-              f"(max {st.max_fgmres}), precond {st.ms_precond:.1f} ms, solves "
+              f"(max {st.max_fgmres}), qtt_used {st.qtt_used}, precond {st.ms_precond:.1f} ms, solves "
               f"{st.ms_solve:.1f} ms, total {st.ms_total:.1f} ms",
               file=sys.stderr, flush=True)
     torch.cuda.synchronize()
@@ -142,7 +146,11 @@ def main():
     nnzb = valN.numel() // 9
     ctx.close()
 
-    solve_ms = float(np.median([s.newton_solve_ms_median for s in stats]))
+    solve_ms = float(np.median([r.solve_ms for r in recs]))
+    its = np.array([r.fgmres_iterations for r in recs])
+    sms = np.array([r.solve_ms for r in recs])
+    print("newton solves: iterations " + " ".join(str(int(i)) for i in its),
+          file=sys.stderr, flush=True)
     fg = [s.fgmres_iterations / max(s.pdip_iterations, 1) for s in stats]
     sp_avg = sp_ms / max(sp_n, 1)
     sp_bytes = spmv_bytes(nnzb, n)
@@ -166,12 +174,24 @@ def main():
                         f"mu {sc.mu}, h {sc.h}",
             "qtt_cores": a.precision, "qtt_eps": a.eps, "qtt_rmax": a.rmax,
             "qtt_rmax_s": a.rmax_s, "fgmres": f"FGMRES({a.restart}) to 1e-8",
-            "pdip_gap_tol": 1e-8,
+            "pdip_gap_tol": 1e-8, "qtt_mode": a.qtt_mode,
         },
+        "qtt_used": [s.qtt_used for s in stats],
+        "trial_iterations": {"qtt": [s.qtt_trial_iterations for s in stats],
+                             "block_jacobi": [s.plain_trial_iterations for s in stats]},
         "newton_solve_ms": solve_ms,
         "qtt_ranks_last": {"X": ranks_x, "S": ranks_s,
                            "ns_iterations": pst.ns_iterations,
                            "probe_residual": pst.probe_residual},
+        "newton_solves": {
+            "count": int(len(recs)),
+            "ms": {"median": solve_ms, "p90": float(np.percentile(sms, 90)),
+                   "max": float(sms.max()), "mean": float(sms.mean())},
+            "fgmres_iterations": {"median": float(np.median(its)),
+                                  "p90": float(np.percentile(its, 90)),
+                                  "max": int(its.max()), "mean": float(its.mean())},
+            "max_rel_residual": float(max(r.rel_residual for r in recs)),
+        },
         "pdip_iterations": [s.pdip_iterations for s in stats],
         "fgmres_iterations_per_newton": fg,
         "contacts": [s.n_contacts for s in stats],

@@ -233,6 +233,24 @@ typedef struct {
  * QTP_NOT_CONVERGED when pdip_maxit is reached. */
 qtp_status qtp_pdip_solve(qtp_ctx ctx, qtp_step_stats* stats);
 
+/* One Newton step of the last PDIP solve: its PDIP iteration, the FGMRES
+ * iterations and wall milliseconds of the kept solve (the preconditioner
+ * already built), the milliseconds spent building preconditioners for it,
+ * whether the QTT inverse was applied, and the final relative residual. */
+typedef struct {
+  int pdip_iteration;
+  int fgmres_iterations;
+  int used_qtt;
+  double solve_ms;
+  double precond_ms;
+  double rel_residual;
+} qtp_newton_record;
+
+/* Copies up to `capacity` records of the last PDIP solve into host memory
+ * and returns how many the solve made (which may exceed capacity), or a
+ * negative status. */
+int qtp_get_newton_log(qtp_ctx ctx, qtp_newton_record* records_host, int capacity);
+
 /* Impulses of the last PDIP solve in the contact frame, physical units
  * (N s): [nc][3] double. */
 qtp_status qtp_get_impulses(qtp_ctx ctx, double* gamma);

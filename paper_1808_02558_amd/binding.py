@@ -76,6 +76,12 @@ class StepStats(ctypes.Structure):
                 ("warm_iterations", ctypes.c_int)]
 
 
+class NewtonRecord(ctypes.Structure):
+    _fields_ = [("pdip_iteration", ctypes.c_int), ("fgmres_iterations", ctypes.c_int),
+                ("used_qtt", ctypes.c_int), ("solve_ms", ctypes.c_double),
+                ("precond_ms", ctypes.c_double), ("rel_residual", ctypes.c_double)]
+
+
 _lib = None
 
 _P = ctypes.c_void_p
@@ -120,6 +126,7 @@ SIGNATURES = {
     "qtp_profile": (_I, [_P, _I]),
     "qtp_get_kernel_time": (_I, [_P, ctypes.c_char_p, _P, _P]),
     "qtp_get_qtt_ranks": (_I, [_P, _I, _P]),
+    "qtp_get_newton_log": (_I, [_P, _P, _I]),
     "qtp_get_qtt_cores": (_I, [_P, _I, _P, _I64]),
 }
 
@@ -374,6 +381,15 @@ class Context:
         self._check(self.lib.qtp_get_kernel_time(self.h, name.encode(),
                                                  ctypes.byref(ms), ctypes.byref(cnt)))
         return ms.value, cnt.value
+
+    def qtp_get_newton_log(self):
+        """Per-Newton-step records of the last PDIP solve."""
+        cnt = self.lib.qtp_get_newton_log(self.h, None, 0)
+        if cnt < 0:
+            raise QtpError(cnt, "newton log unavailable")
+        buf = (NewtonRecord * max(cnt, 1))()
+        self.lib.qtp_get_newton_log(self.h, buf, cnt)
+        return [buf[i] for i in range(cnt)]
 
     def qtp_get_qtt_ranks(self, which):
         buf = (ctypes.c_int32 * 64)()

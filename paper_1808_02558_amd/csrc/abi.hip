@@ -600,6 +600,14 @@ qtp_status qtp_get_kernel_time(qtp_ctx ctx, const char* name, double* ms_total,
   });
 }
 
+int qtp_get_newton_log(qtp_ctx ctx, qtp_newton_record* records_host, int capacity) {
+  if (!ctx || capacity < 0 || (capacity > 0 && !records_host)) return QTP_E_ARG;
+  const auto& log = ctx->c.pd.log;
+  const int n = (int)log.size();
+  for (int i = 0; i < n && i < capacity; ++i) records_host[i] = log[i];
+  return n;
+}
+
 int qtp_get_qtt_ranks(qtp_ctx ctx, int which, int32_t* ranks_host) {
   if (!ctx || !ranks_host || (which != 0 && which != 1)) return QTP_E_ARG;
   const qtp::Qtt& q = which == 0 ? ctx->c.A : ctx->c.X;

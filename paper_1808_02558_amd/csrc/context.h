@@ -72,6 +72,7 @@ struct Pdip {
   DevBuf lam, dlam;                    // [2 nc]: cone part then gamma_n part
   DevBuf part;                         // reduction partials
   bool have_gamma = false;
+  std::vector<qtp_newton_record> log; // one record per Newton step
 };
 
 // Optional event timing of selected kernels on the context's stream.

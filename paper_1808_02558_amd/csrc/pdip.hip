@@ -329,6 +329,7 @@ static int pdip_run(Ctx& c, qtp_step_stats* st, bool warm) {
   st->qtt_trial_iterations = 0;
   st->plain_trial_iterations = 0;
   c.auto_qtt = false;
+  pd.log.clear();
   std::vector<double> solve_ms;
   const double t_begin = now_ms();
   if (nc == 0) {
@@ -385,6 +386,7 @@ static int pdip_run(Ctx& c, qtp_step_stats* st, bool warm) {
         nc, mu, t, slot, qp.diagpos.as<int32_t>(), gamma, lam, u,
         qp.valN.as<double>(), c.val.as<double>(), pd.rhs.as<double>());
     QTP_CHECK_LAUNCH();
+    const double pre0 = st->ms_precond;
     double t0 = now_ms();
     precond_factor(c);
     c.have_precond = true;
@@ -444,6 +446,8 @@ static int pdip_run(Ctx& c, qtp_step_stats* st, bool warm) {
     }
     solve_ms.push_back(sms);
     st->max_fgmres = std::max(st->max_fgmres, ss.iterations);
+    pd.log.push_back(qtp_newton_record{it, ss.iterations, c.use_qtt ? 1 : 0, sms,
+                                       st->ms_precond - pre0, ss.rel_residual});
     // Delta lambda and the step bound
     dlam_kernel<<<nb, kT, 0, s>>>(nc, mu, t, slot, gamma, dgamma, lam, dlam, part);
     QTP_CHECK_LAUNCH();

@@ -228,12 +228,14 @@ __global__ void probe_kernel(int64_t n, double* __restrict__ z1,
 }
 
 // out[0] = max_s sum_j |A_sj| over rows (Gershgorin bound); one block.
+// Per-block maximum Gershgorin row sum of the scaled matrix (dummy rows of
+// the identity contribute 1); the host takes the maximum of the partials.
 __global__ void gershgorin_kernel(int nslots, const int32_t* __restrict__ rp,
                                   const double* __restrict__ val,
-                                  double* __restrict__ out) {
+                                  double* __restrict__ part) {
   __shared__ double sh[kT];
-  double m = 1.0;  // dummy rows of the identity
-  for (int s = threadIdx.x; s < nslots; s += kT) {
+  double m = 1.0;
+  for (int s = blockIdx.x * kT + threadIdx.x; s < nslots; s += gridDim.x * kT) {
     double r0 = 0.0, r1 = 0.0, r2 = 0.0;
     for (int q = rp[s]; q < rp[s + 1]; ++q) {
       const double* b = val + (int64_t)q * 9;
@@ -249,7 +251,7 @@ __global__ void gershgorin_kernel(int nslots, const int32_t* __restrict__ rp,
     if (threadIdx.x < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[0] = sh[0];
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
 int trunc_rank(const std::vector<double>& ev, double delta2, int cap) {
@@ -679,13 +681,16 @@ void build_inverse(Ctx& c, int hot) {
     load_from(s, c.X, X);
     iters = c.cfg.ns_iters_hot;
   } else {
-    sc.g.ensure(sizeof(double));
-    gershgorin_kernel<<<1, kT, 0, s>>>(c.nslots, c.rp.as<int32_t>(), c.sval.as<double>(),
-                                       sc.g.as<double>());
+    const int nb = std::max(1, std::min(1024, div_up(c.nslots, kT)));
+    sc.partial.ensure(sizeof(double) * 1024);
+    gershgorin_kernel<<<nb, kT, 0, s>>>(c.nslots, c.rp.as<int32_t>(), c.sval.as<double>(),
+                                        sc.partial.as<double>());
     QTP_CHECK_LAUNCH();
-    double lam = 1.0;
-    QTP_HIP(hipMemcpyAsync(&lam, sc.g.get(), sizeof(double), hipMemcpyDeviceToHost, s));
+    std::vector<double> hp(nb);
+    QTP_HIP(hipMemcpyAsync(hp.data(), sc.partial.get(), sizeof(double) * nb,
+                           hipMemcpyDeviceToHost, s));
     QTP_HIP(hipStreamSynchronize(s));
+    const double lam = *std::max_element(hp.begin(), hp.end());
     scaled_identity(s, d, 1.0 / lam, X);
   }
   double best = b.probe(X);
