@@ -139,8 +139,11 @@ def main():
     qa_ms, qa_n = ctx.qtp_get_kernel_time("qtt_apply")
     cg_ms, cg_n = ctx.qtp_get_kernel_time("cgs2")
     ctx.qtp_profile(False)
-    ranks_x = ctx.qtp_get_qtt_ranks(1)
-    ranks_s = ctx.qtp_get_qtt_ranks(0)
+    try:
+        ranks_x = ctx.qtp_get_qtt_ranks(1)
+        ranks_s = ctx.qtp_get_qtt_ranks(0)
+    except binding.QtpError:  # block-Jacobi only: no QTT was built
+        ranks_x = ranks_s = None
     pst = ctx.qtp_get_precond_stats()
     _, _, valN, _ = ctx.qtp_get_qp(sc.log2n)
     nnzb = valN.numel() // 9

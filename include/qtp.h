@@ -71,7 +71,7 @@ typedef struct {
   int ns_iters_hot;     /* Newton-Schulz iterations for a hot-started inverse */
   int solve_mode;       /* 0: X * rhs + iterative refinement, 1: FGMRES */
   double solve_tol;     /* relative residual of the Newton-step solve */
-  int fgmres_restart;   /* FGMRES restart length m */
+  int fgmres_restart;   /* FGMRES restart length m, 1..32 */
   int fgmres_maxit;     /* total FGMRES (or refinement) iteration cap */
   double pdip_gap_tol;  /* PDIP stop: gap / m */
   double pdip_dual_tol; /* PDIP stop: |r_dual|_inf in scaled units */

@@ -60,8 +60,8 @@ void qtp::Ctx::flush_timers() {
       QTP_HIP(hipEventElapsedTime(&ms, e.first, e.second));
       kv.second.ms += ms;
       kv.second.count += 1;
-      (void)hipEventDestroy(e.first);
-      (void)hipEventDestroy(e.second);
+      event_pool.push_back(e.first);
+      event_pool.push_back(e.second);
     }
     kv.second.pending.clear();
   }
@@ -72,8 +72,8 @@ void qtp::Ctx::check_cfg() {
   QTP_REQUIRE(cfg.qtt_rmax >= 1 && cfg.qtt_rmax <= 64, QTP_E_ARG, "qtt_rmax out of [1,64]");
   QTP_REQUIRE(cfg.qtt_rmax_s >= 1 && cfg.qtt_rmax_s <= 64, QTP_E_ARG, "qtt_rmax_s out of [1,64]");
   QTP_REQUIRE(cfg.qtt_eps > 0.0 && cfg.qtt_eps < 1.0, QTP_E_ARG, "qtt_eps out of (0,1)");
-  QTP_REQUIRE(cfg.fgmres_restart >= 1 && cfg.fgmres_restart <= 63, QTP_E_ARG,
-              "fgmres_restart out of [1,63]");
+  QTP_REQUIRE(cfg.fgmres_restart >= 1 && cfg.fgmres_restart <= qtp::kArnMaxRestart,
+              QTP_E_ARG, "fgmres_restart out of [1,32]");
   QTP_REQUIRE(cfg.fgmres_maxit >= 1, QTP_E_ARG, "fgmres_maxit < 1");
   QTP_REQUIRE(cfg.solve_tol > 0.0, QTP_E_ARG, "solve_tol <= 0");
   QTP_REQUIRE(cfg.solve_mode == 0 || cfg.solve_mode == 1, QTP_E_ARG, "bad solve_mode");

@@ -82,4 +82,27 @@ class DevBuf {
   size_t bytes_ = 0;
 };
 
+// Pinned, device-visible host memory (coherent), allocated once.
+class HostBuf {
+ public:
+  HostBuf() = default;
+  HostBuf(const HostBuf&) = delete;
+  HostBuf& operator=(const HostBuf&) = delete;
+  ~HostBuf() {
+    if (ptr_) (void)hipHostFree(ptr_);
+  }
+  bool empty() const { return ptr_ == nullptr; }
+  void alloc(size_t bytes) {
+    if (ptr_) return;
+    QTP_HIP(hipHostMalloc(&ptr_, bytes, hipHostMallocDefault));
+    QTP_HIP(hipHostGetDevicePointer(&dev_, ptr_, 0));
+  }
+  template <class T> T* host() const { return static_cast<T*>(ptr_); }
+  template <class T> T* dev() const { return static_cast<T*>(dev_); }
+
+ private:
+  void* ptr_ = nullptr;
+  void* dev_ = nullptr;
+};
+
 }  // namespace qtp

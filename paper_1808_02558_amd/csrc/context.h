@@ -86,13 +86,27 @@ struct BuildCache;
 void destroy_build_cache(BuildCache* bc);
 
 struct Ctx {
-  ~Ctx() { destroy_build_cache(bcache); }
+  ~Ctx() {
+    destroy_build_cache(bcache);
+    for (hipEvent_t e : event_pool) (void)hipEventDestroy(e);
+  }
   BuildCache* bcache = nullptr;  // persistent scratch of the QTT construction
   qtp_config cfg{};
   bool profile = false;
   std::vector<std::pair<std::string, KTimer>> timers;
+  std::vector<hipEvent_t> event_pool;  // recycled timing events
   KTimer& timer(const char* name);
   void flush_timers();
+  hipEvent_t take_event() {
+    if (event_pool.empty()) {
+      hipEvent_t e;
+      QTP_HIP(hipEventCreate(&e));
+      return e;
+    }
+    hipEvent_t e = event_pool.back();
+    event_pool.pop_back();
+    return e;
+  }
   hipStream_t stream = nullptr;
   std::string err;
 
@@ -132,6 +146,9 @@ struct Ctx {
   DevBuf V, Z, w, r, t1, t2;  // Krylov vectors
   DevBuf partial, scal;       // reductions
   DevBuf flag;                // int flags
+  DevBuf arn_d, arn_partial;           // Arnoldi solve state
+  HostBuf arn_status;                  // residual estimates for the host
+  int64_t arn_tag = 0;                 // last status tag issued
 
   void check_cfg();
 };
@@ -144,8 +161,8 @@ struct TimedLaunch {
   TimedLaunch(Ctx& ctx, const char* name) : c(ctx) {
     if (!c.profile) return;
     t = &c.timer(name);
-    QTP_HIP(hipEventCreate(&a));
-    QTP_HIP(hipEventCreate(&b));
+    a = c.take_event();
+    b = c.take_event();
     QTP_HIP(hipEventRecord(a, c.stream));
   }
   ~TimedLaunch() {

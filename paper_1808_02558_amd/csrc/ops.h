@@ -51,6 +51,51 @@ void add_inplace(hipStream_t s, const double* x, double* y, int64_t n);
 // Non-finite check: out[0] = 1 if any entry of x is NaN/Inf else 0.
 void any_nonfinite(hipStream_t s, const double* x, int64_t n, int* out);
 
+// ---- Arnoldi steps of FGMRES (arnoldi.hip) ------------------------------------
+constexpr int kArnMaxRestart = 32;  // longest restart cycle
+constexpr int kArnLd = 64;          // leading dimension of the Hessenberg columns
+constexpr int kArnRing = 64;        // entries of the host status ring (power of 2)
+// Offsets (in doubles) of the device solve state Arnoldi::d.
+enum : int {
+  kArnH1 = 0,      // first Gram-Schmidt coefficients of the current step
+  kArnH2 = 64,     // second (re-orthogonalisation) coefficients
+  kArnInv = 128,   // 1 / h_{j+1,j} of the last step (0 on breakdown)
+  kArnG = 192,     // rotated right-hand side beta e_1
+  kArnCs = 256,    // Givens cosines
+  kArnSn = 320,    // Givens sines
+  kArnY = 384,     // least-squares solution of the cycle
+  kArnH = 448,     // Hessenberg, column j at kArnH + j * kArnLd
+  kArnDoubles = kArnH + kArnLd * kArnMaxRestart
+};
+// One residual estimate, written by the device into pinned host memory.
+struct ArnStatus {
+  double res;   // |g_{j+1}|: the least-squares residual after step j
+  double hn;    // h_{j+1,j}
+  double pad;
+  int64_t tag;  // written last; identifies the step
+};
+struct Arnoldi {
+  double* d = nullptr;          // kArnDoubles doubles (device)
+  double* partial = nullptr;    // arnoldi_partial_doubles(n) doubles (device)
+  ArnStatus* status = nullptr;  // kArnRing entries, device view of pinned memory
+};
+size_t arnoldi_partial_doubles(int64_t n);
+// V_j = (src - sum_{l<nprev} h2_l V_l) * inv, inv = d[kArnInv] when nprev > 0
+// else inv0 (nprev == 0 also sets g = beta e_1); then zout = L^-T L^-1 V_j
+// (full = 1) or L^-1 V_j (full = 0).  src may alias vj.
+void arnoldi_next(hipStream_t s, const Arnoldi& a, int nprev, const double* V,
+                  int64_t n, int nslots, double inv0, double beta, const double* src,
+                  double* vj, const double* Linv, int full, double* zout);
+// h1 = V_{0..nvec-1}^T w
+void arnoldi_dots(hipStream_t s, const Arnoldi& a, int nvec, const double* V,
+                  int64_t n, const double* w);
+// w -= V h1; h2 = V^T w; Hessenberg column nvec - 1, Givens rotation and the
+// status entry `tag`.
+void arnoldi_orth(hipStream_t s, const Arnoldi& a, int nvec, const double* V,
+                  int64_t n, double* w, int64_t tag);
+// d[kArnY..] = least-squares solution of the first jend columns
+void arnoldi_solve(hipStream_t s, const Arnoldi& a, int jend);
+
 // ---- block-Jacobi scaling (blas1.hip) ---------------------------------------
 // Linv[s][6] = lower triangle (row-major: l00 l10 l11 l20 l21 l22) of the
 // inverse of chol(A_ss), the diagonal 3x3 block of block row s.

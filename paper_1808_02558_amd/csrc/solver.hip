@@ -87,16 +87,64 @@ double residual(Ctx& c, const double* rhs, const double* x, double* r) {
   return norm2(c, r);
 }
 
+Arnoldi arnoldi_state(Ctx& c) {
+  if (c.arn_status.empty()) {
+    c.arn_status.alloc(sizeof(ArnStatus) * kArnRing);
+    ArnStatus* h = c.arn_status.host<ArnStatus>();
+    for (int i = 0; i < kArnRing; ++i) h[i] = ArnStatus{0.0, 0.0, 0.0, -1};
+  }
+  c.arn_d.ensure(sizeof(double) * kArnDoubles);
+  c.arn_partial.ensure(sizeof(double) * arnoldi_partial_doubles(c.n));
+  Arnoldi a;
+  a.d = c.arn_d.as<double>();
+  a.partial = c.arn_partial.as<double>();
+  a.status = c.arn_status.dev<ArnStatus>();
+  return a;
+}
+
+// Waits until the device has written status entry `tag`.  Polls the stream
+// now and then so that a failed or finished stream cannot leave the host
+// spinning.
+ArnStatus wait_status(Ctx& c, int64_t tag) {
+  volatile ArnStatus* e = c.arn_status.host<ArnStatus>() + (tag & (kArnRing - 1));
+  int64_t spins = 0;
+  while (__atomic_load_n(&e->tag, __ATOMIC_ACQUIRE) != tag) {
+    if ((++spins & 1023) == 0) {
+      const hipError_t q = hipStreamQuery(c.stream);
+      if (q == hipSuccess) {
+        if (__atomic_load_n(&e->tag, __ATOMIC_ACQUIRE) == tag) break;
+        throw Error(QTP_E_HIP, "FGMRES: residual estimate missing after the stream drained");
+      }
+      if (q != hipErrorNotReady) QTP_HIP(q);
+    }
+    __builtin_ia32_pause();
+  }
+  ArnStatus out;
+  out.res = e->res;
+  out.hn = e->hn;
+  out.pad = 0.0;
+  out.tag = tag;
+  return out;
+}
+
+// Right-preconditioned FGMRES(m).  Within a restart cycle the host queues step
+// j and only then reads the residual estimate of step j - 1, so the device
+// always has the next step queued; a step queued after convergence is
+// discarded (it touches only column j of the Hessenberg and entries >= j of
+// g).  Each cycle ends with the true residual rhs - S x.
 int fgmres(Ctx& c, const double* rhs, double* x, qtp_solve_stats* st) {
   const int64_t n = c.n;
   const int m = c.cfg.fgmres_restart;
   ensure_krylov(c, m);
+  const Arnoldi a = arnoldi_state(c);
   double* V = c.V.as<double>();
   double* Z = c.Z.as<double>();
   double* r = c.r.as<double>();
-  double* sc = c.scal.as<double>();
-  double* part = c.partial.as<double>();
+  double* t1 = c.t1.as<double>();
+  double* t2 = c.t2.as<double>();
   const double tol = c.cfg.solve_tol;
+  const bool qtt = c.have_inverse && c.use_qtt;
+  const double* Linv = c.Linv.as<double>();
 
   const double bnorm = norm2(c, rhs);
   QTP_HIP(hipMemsetAsync(x, 0, sizeof(double) * n, c.stream));
@@ -106,68 +154,70 @@ int fgmres(Ctx& c, const double* rhs, double* x, qtp_solve_stats* st) {
     st->rel_residual = 0.0;
     return QTP_OK;
   }
-  QTP_HIP(hipMemcpyAsync(r, rhs, sizeof(double) * n, hipMemcpyDeviceToDevice,
-                         c.stream));
+  const void* qcores = nullptr;
+  if (qtt) {
+    qcores = c.X.cores.get();
+    if (c.cfg.precision != 0) {
+      ensure_lp_cores(c, c.X);
+      qcores = c.X.cores_lp.get();
+    }
+    c.qtt_work.ensure(qtt_apply_workspace(c.X.d, c.X.ranks.data(), c.cfg.precision));
+  }
   double beta = bnorm;
+  const double* res_src = rhs;  // x = 0: the first residual is rhs itself
   int it = 0;
-  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
-  std::vector<double> hbuf(130);
-  bool done = false;
-  while (!done && it < c.cfg.fgmres_maxit) {
-    if (beta <= tol * bnorm) break;
-    axpby(c.stream, 1.0 / beta, r, 0.0, V, n);
-    std::fill(g.begin(), g.end(), 0.0);
-    g[0] = beta;
-    int jend = 0;
-    for (int j = 0; j < m; ++j) {
+  std::vector<int64_t> tags(m);
+  while (it < c.cfg.fgmres_maxit && beta > tol * bnorm) {
+    const int jmax = std::min(m, c.cfg.fgmres_maxit - it);
+    int jend = jmax;
+    for (int j = 0; j < jmax; ++j) {
       double* vj = V + (int64_t)j * n;
       double* zj = Z + (int64_t)j * n;
       double* w = V + (int64_t)(j + 1) * n;
-      precond_apply(c, vj, zj);
+      {
+        TimedLaunch tl(c, "arnoldi_next");
+        arnoldi_next(c.stream, a, j == 0 ? 0 : j, V, n, c.nslots, 1.0 / beta, beta,
+                     j == 0 ? res_src : vj, vj, Linv, qtt ? 0 : 1, qtt ? t1 : zj);
+      }
+      if (qtt) {
+        {
+          TimedLaunch tl(c, "qtt_apply");
+          qtt_apply(c.stream, c.X.d, c.X.ranks.data(), qcores, c.cfg.precision, t1, t2,
+                    c.qtt_work.get());
+        }
+        bj_apply(c.stream, c.nslots, n, Linv, 1, t2, zj);
+      }
       spmv(c, zj, w);
       {
-        TimedLaunch tl(c, "cgs2");
-        multi_dot(c.stream, j + 1, V, n, w, n, part, sc);
-        cgs_update_dot(c.stream, j + 1, V, n, sc, w, n, part, sc + 64);
-        cgs_update_norm2(c.stream, j + 1, V, n, sc + 64, w, n, part, sc + 128);
+        TimedLaunch tl(c, "arnoldi_dots");
+        arnoldi_dots(c.stream, a, j + 1, V, n, w);
       }
-      QTP_HIP(hipMemcpyAsync(hbuf.data(), sc, sizeof(double) * 129,
-                             hipMemcpyDeviceToHost, c.stream));
-      QTP_HIP(hipStreamSynchronize(c.stream));
-      double* Hj = &H[(size_t)j * (m + 1)];  // column j, length m+1
-      for (int i = 0; i <= j; ++i) Hj[i] = hbuf[i] + hbuf[64 + i];
-      const double hn = std::sqrt(hbuf[128]);
-      Hj[j + 1] = hn;
-      if (!std::isfinite(hn)) throw Error(QTP_E_NUMERIC, "FGMRES breakdown (NaN)");
-      if (hn > 0.0) axpby(c.stream, 1.0 / hn, w, 0.0, w, n);
-      for (int i = 0; i < j; ++i) {
-        const double t = cs[i] * Hj[i] + sn[i] * Hj[i + 1];
-        Hj[i + 1] = -sn[i] * Hj[i] + cs[i] * Hj[i + 1];
-        Hj[i] = t;
+      tags[j] = ++c.arn_tag;
+      {
+        TimedLaunch tl(c, "arnoldi_orth");
+        arnoldi_orth(c.stream, a, j + 1, V, n, w, tags[j]);
       }
-      const double den = std::hypot(Hj[j], Hj[j + 1]);
-      cs[j] = Hj[j] / den;
-      sn[j] = Hj[j + 1] / den;
-      Hj[j] = den;
-      Hj[j + 1] = 0.0;
-      g[j + 1] = -sn[j] * g[j];
-      g[j] = cs[j] * g[j];
-      ++it;
-      jend = j + 1;
-      if (std::fabs(g[j + 1]) <= tol * bnorm || it >= c.cfg.fgmres_maxit || hn == 0.0)
-        break;
+      if (j >= 1) {
+        const ArnStatus e = wait_status(c, tags[j - 1]);
+        if (!std::isfinite(e.res) || !std::isfinite(e.hn))
+          throw Error(QTP_E_NUMERIC, "FGMRES breakdown (NaN)");
+        if (e.res <= tol * bnorm || e.hn == 0.0) {
+          jend = j;
+          break;
+        }
+      }
     }
-    // back substitution H y = g, then x += Z y
-    for (int i = jend - 1; i >= 0; --i) {
-      double t = g[i];
-      for (int k = i + 1; k < jend; ++k) t -= H[(size_t)k * (m + 1) + i] * y[k];
-      y[i] = t / H[(size_t)i * (m + 1) + i];
+    if (jend == jmax) {
+      const ArnStatus e = wait_status(c, tags[jmax - 1]);
+      if (!std::isfinite(e.res) || !std::isfinite(e.hn))
+        throw Error(QTP_E_NUMERIC, "FGMRES breakdown (NaN)");
     }
-    QTP_HIP(hipMemcpyAsync(sc + 192, y.data(), sizeof(double) * jend,
-                           hipMemcpyHostToDevice, c.stream));
-    multi_axpy(c.stream, jend, Z, n, sc + 192, x, n);
+    it += jend;
+    arnoldi_solve(c.stream, a, jend);
+    multi_axpy(c.stream, jend, Z, n, a.d + kArnY, x, n);
     beta = residual(c, rhs, x, r);
-    if (beta <= tol * bnorm) done = true;
+    res_src = r;
+    if (!std::isfinite(beta)) throw Error(QTP_E_NUMERIC, "FGMRES: residual not finite");
   }
   st->iterations = it;
   st->rel_residual = beta / bnorm;
@@ -260,9 +310,7 @@ void precond_apply(Ctx& c, const double* v, double* z) {
 int newton_solve(Ctx& c, const double* rhs, double* x, qtp_solve_stats* st) {
   QTP_REQUIRE(c.have_matrix, QTP_E_STATE, "no Newton matrix loaded");
   QTP_REQUIRE(c.have_precond, QTP_E_STATE, "preconditioner not built");
-  hipEvent_t e0, e1;
-  QTP_HIP(hipEventCreate(&e0));
-  QTP_HIP(hipEventCreate(&e1));
+  hipEvent_t e0 = c.take_event(), e1 = c.take_event();
   QTP_HIP(hipEventRecord(e0, c.stream));
   int rc = c.cfg.solve_mode == 0 ? refine(c, rhs, x, st) : fgmres(c, rhs, x, st);
   QTP_HIP(hipEventRecord(e1, c.stream));
@@ -270,8 +318,8 @@ int newton_solve(Ctx& c, const double* rhs, double* x, qtp_solve_stats* st) {
   float ms = 0.f;
   QTP_HIP(hipEventElapsedTime(&ms, e0, e1));
   st->ms = ms;
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  c.event_pool.push_back(e0);
+  c.event_pool.push_back(e1);
   return rc;
 }
 

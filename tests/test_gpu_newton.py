@@ -111,6 +111,31 @@ def test_newton_solve_block_jacobi_fgmres(torch, ctx, name, it):
     assert fwd <= 1e-8, fwd
 
 
+@pytest.mark.parametrize("restart", [1, 5, 32])
+def test_fgmres_restart_cycles_match_oracle(torch, ctx, restart):
+    """Restart cycles and the lagged convergence test: the GPU solve stops at
+    the oracle's iteration count (within rounding) and meets the residual."""
+    from oracle import krylov, precond
+    snap = cases.newton_snapshots("small_box")
+    d = snap["log2n"]
+    it = 5
+    Spad, rp, col, val = load_matrix(torch, snap, it)
+    rhs = helpers.pad_vector(snap["result"].history[it]["rhs"], snap["slot"], d)
+    Linv = precond.block_jacobi_inverse_factors(Spad.toarray())
+    _, its_ref, _ = krylov.fgmres(lambda v: Spad @ v, lambda v: Linv.T @ (Linv @ v),
+                                  rhs, tol=1e-10, restart=restart, maxit=5000)
+    ctx.qtp_set_config(solve_mode=1, solve_tol=1e-10, fgmres_restart=restart,
+                       fgmres_maxit=5000)
+    ctx.qtp_set_newton_matrix(d, rp, col, val)
+    ident = helpers.flat_cores(tt.qtt_identity(d))
+    ctx.qtp_precond_load_qtt(d, [1] * (d + 1), dev(torch, ident))
+    x = torch.empty(1 << d, dtype=torch.float64, device="cuda")
+    rc, st = ctx.qtp_newton_solve(dev(torch, rhs), x)
+    res = np.linalg.norm(rhs - Spad @ x.cpu().numpy()) / np.linalg.norm(rhs)
+    assert rc == 0 and res <= 1.01e-10, (rc, res, st.iterations)
+    assert abs(st.iterations - its_ref) <= max(2, its_ref // 20), (st.iterations, its_ref)
+
+
 def test_newton_solve_with_oracle_qtt_inverse(torch, ctx):
     """Direct solve with a QTT inverse plus refinement (tiny box, 2^9)."""
     snap = cases.newton_snapshots("tiny_box")
