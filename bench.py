@@ -2,12 +2,19 @@
 
 One step is one frictional-contact time step of the whole hot path on the
 GPU: contact detection and ordering, assembly of N and r, the PDIP loop
-(per Newton iteration: barrier blocks, block-Jacobi + QTT compression and
-Newton-Schulz inverse update, FGMRES to 1e-8), and integration.  Workload:
-the seeded rectangular hopper fill of 131,072 spheres (radius uniform in
-[0.8, 1.2] cm, mu = 0.4, h = 1e-3 s), ~3.4e5 contacts padded to 2^20.
+(per Newton iteration: barrier blocks, block-Jacobi factors, the QTT inverse
+where the preconditioner mode uses it, FGMRES to 1e-8), and integration.
+Workload: the seeded rectangular hopper fill of 131,072 spheres (radius
+uniform in [0.8, 1.2] cm, mu = 0.4, h = 1e-3 s), ~3.4e5 contacts padded to
+2^20 unknowns.
 
-    python bench.py [--steps K] [--warmup W] [--precision f64|f32|bf16]
+After the timed steps, each form of the method solves the first time step
+from the same initial state: the QTT-preconditioned solve with FP64, FP32 and
+BF16 cores and the block-Jacobi-only solve; then the learned warm start is
+trained on two solved steps and compared with the cold start on the next
+step.  Impulses are compared with the FP64 QTT form.
+
+    python bench.py [--steps K] [--warmup W] [--no-forms] [--no-cpu-baseline]
 
 Prints one JSON line.  Only one GPU is used; --gpus above 1 exits.
 """
@@ -24,6 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
 
 
 def spmv_bytes(nnzb, n):
@@ -33,10 +41,16 @@ def spmv_bytes(nnzb, n):
     return 72 * nnzb + 4 * nnzb + 4 * (nslots + 1) + 16 * n
 
 
-def cpu_baseline(precision_note):
-    """The oracle's time step on a bounded hopper sample, scaled to 2^20."""
-    import numpy as np
+def qtt_apply_work(ranks, n, prec):
+    """Flops (4 N sum_k r_{k-1} r_k) and minimum bytes (x in and y out in
+    FP64, the cores once) of one QTT matrix-vector product."""
+    pairs = sum(ranks[k] * ranks[k + 1] for k in range(len(ranks) - 1))
+    core_bytes = 4 * pairs * {"f64": 8, "f32": 4, "bf16": 2}[prec]
+    return 4.0 * n * pairs, 16.0 * n + core_bytes
 
+
+def cpu_baseline():
+    """The oracle's time step on a bounded hopper sample, scaled to 2^20."""
     import scenes
     from oracle import pdip
 
@@ -66,6 +80,145 @@ def cpu_baseline(precision_note):
     }
 
 
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_context(binding, torch, sc, **cfg):
+    import numpy as np
+
+    def dev(x):
+        return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+    ctx = binding.Context(**cfg)
+    ctx.qtp_set_bodies(dev(sc.x), dev(sc.v), dev(sc.w), dev(sc.radius), dev(sc.mass))
+    ctx.qtp_set_walls(sc.planes)
+    ctx.qtp_set_params(sc.mu, sc.h, sc.delta, sc.gravity, sc.log2n)
+    return ctx
+
+
+def rel_err(g, ref):
+    import numpy as np
+    return float(np.linalg.norm(g - ref) / np.linalg.norm(ref))
+
+
+def step_summary(st):
+    return {"ms": st.ms_total, "pdip_iterations": st.pdip_iterations,
+            "fgmres_iterations": st.fgmres_iterations, "max_fgmres": st.max_fgmres,
+            "precond_ms": st.ms_precond, "solve_ms": st.ms_solve,
+            "converged": bool(st.converged)}
+
+
+def qtt_form(binding, torch, sc, base, prec):
+    """First time step with the QTT inverse applied at every Newton step."""
+    import numpy as np
+    ctx = make_context(binding, torch, sc, **dict(base, qtt_mode=1, precision=prec))
+    try:
+        ctx.qtp_profile(True)
+        rc, st = ctx.qtp_step()
+        g = ctx.qtp_get_impulses(st.n_contacts).cpu().numpy()
+        qa_ms, qa_n = ctx.qtp_get_kernel_time("qtt_apply")
+        ranks = ctx.qtp_get_qtt_ranks(1)
+        recs = ctx.qtp_get_newton_log()
+        ctx.qtp_profile(False)
+    finally:
+        ctx.close()
+    n = 1 << sc.log2n
+    out = step_summary(st)
+    out["newton_solve_ms_median"] = float(np.median([r.solve_ms for r in recs]))
+    if qa_n:
+        avg = qa_ms / qa_n
+        flops, nbytes = qtt_apply_work(ranks, n, prec)
+        tf = flops / (avg * 1e-3) / 1e12
+        out["qtt_apply"] = {
+            "ms_avg": avg, "launches": qa_n, "ranks_last": ranks, "tflops": tf,
+            "frac_of_peak_flops": tf / PEAK_TFLOPS[prec],
+            "min_bytes_gbs": nbytes / (avg * 1e-3) / 1e9}
+    log(f"form qtt {prec}: {st.pdip_iterations} PDIP its, {st.fgmres_iterations} "
+        f"FGMRES its, {st.ms_total:.1f} ms")
+    return out, g
+
+
+def simple_form(binding, torch, sc, cfg, label):
+    ctx = make_context(binding, torch, sc, **cfg)
+    try:
+        rc, st = ctx.qtp_step()
+        g = ctx.qtp_get_impulses(st.n_contacts).cpu().numpy()
+    finally:
+        ctx.close()
+    log(f"form {label}: {st.pdip_iterations} PDIP its, {st.fgmres_iterations} FGMRES "
+        f"its, {st.ms_total:.1f} ms")
+    return step_summary(st), g
+
+
+def mlp_form(binding, torch, sc, base, train_steps=2, epochs=6, batch=4096, lr=1e-3):
+    """Learned warm start: train the network on the solved impulses of the
+    first time steps (the library's forward, backward and Adam kernels), then
+    solve the next time step from its prediction and from the cold start."""
+    import numpy as np
+
+    import scenes
+    ctx = make_context(binding, torch, sc, **dict(base, warm_start=0))
+    try:
+        Xs, Ys = [], []
+        for _ in range(train_steps):
+            nc = ctx.qtp_detect()
+            ctx.qtp_assemble()
+            Xs.append(ctx.qtp_mlp_features(nc))
+            ctx.qtp_pdip_solve()
+            Ys.append(ctx.qtp_mlp_targets(nc))
+            ctx.qtp_integrate()
+        X = torch.cat(Xs)
+        Y = torch.cat(Ys)
+        params = np.concatenate([p.reshape(-1) for p in scenes.tensors.mlp_init(
+            [11, 128, 128, 128, 3], seed=1000)]).astype(np.float32)
+        ctx.qtp_mlp_set_params(torch.from_numpy(params).cuda())
+        ctx.qtp_mlp_fit_normalization(X)
+        rows = X.shape[0]
+        perm = torch.from_numpy(np.random.default_rng(0).permutation(rows)).cuda()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        first = last = None
+        nsteps = 0
+        for _ in range(epochs):
+            for b0 in range(0, rows, batch):
+                idx = perm[b0:b0 + batch]
+                loss = ctx.qtp_mlp_train_step(X[idx].contiguous(), Y[idx].contiguous(),
+                                              lr=lr)
+                first = loss if first is None else first
+                last = loss
+                nsteps += 1
+        torch.cuda.synchronize()
+        train_ms = (time.perf_counter() - t0) * 1e3
+        nc = ctx.qtp_detect()
+        ctx.qtp_assemble()
+        ctx.qtp_set_config(warm_start=2)
+        rc_w, warm = ctx.qtp_pdip_solve()
+        gw = ctx.qtp_get_impulses(nc).cpu().numpy()
+        ctx.qtp_set_config(warm_start=0)
+        rc_c, cold = ctx.qtp_pdip_solve()
+        gc = ctx.qtp_get_impulses(nc).cpu().numpy()
+    finally:
+        ctx.close()
+    log(f"form mlp: warm {warm.pdip_iterations} PDIP its {warm.ms_pdip:.1f} ms "
+        f"(fallback {warm.warm_fallback}), cold {cold.pdip_iterations} its "
+        f"{cold.ms_pdip:.1f} ms; loss {first:.4f} -> {last:.4f}")
+    return {
+        "training": {"rows": int(rows), "steps_of_data": train_steps, "epochs": epochs,
+                     "adam_steps": nsteps, "batch": batch, "lr": lr,
+                     "loss_first": first, "loss_last": last, "ms": train_ms},
+        "held_out_step": {
+            "warm": {"pdip_iterations": warm.pdip_iterations,
+                     "fgmres_iterations": warm.fgmres_iterations, "ms": warm.ms_pdip,
+                     "fallback": bool(warm.warm_fallback),
+                     "converged": bool(warm.converged)},
+            "cold": {"pdip_iterations": cold.pdip_iterations,
+                     "fgmres_iterations": cold.fgmres_iterations, "ms": cold.ms_pdip,
+                     "converged": bool(cold.converged)},
+            "impulse_rel_diff_warm_vs_cold": rel_err(gw, gc)},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,10 +231,11 @@ def main():
     ap.add_argument("--restart", type=int, default=30)
     ap.add_argument("--ns-iters", type=int, default=6)
     ap.add_argument("--ns-iters-hot", type=int, default=2)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--scene", default="hopper")
     ap.add_argument("--qtt-mode", type=int, default=2, choices=[0, 1, 2],
                     help="0 block-Jacobi only, 1 QTT inverse always, 2 per-step trial")
+    ap.add_argument("--scene", default="hopper")
+    ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {a.gpus}); the "
@@ -98,27 +252,21 @@ def main():
 
     torch.cuda.set_device(0)
     sc = scenes.make_scene(a.scene)
-    ctx = binding.Context(precision=a.precision, qtt_rmax=a.rmax,
-                          qtt_rmax_s=a.rmax_s, qtt_eps=a.eps, solve_mode=1,
-                          solve_tol=1e-8, fgmres_restart=a.restart,
-                          fgmres_maxit=3000, ns_iters=a.ns_iters,
-                          ns_iters_hot=a.ns_iters_hot, qtt_mode=a.qtt_mode)
-
-    def dev(x):
-        return torch.from_numpy(np.ascontiguousarray(x)).cuda()
-
-    ctx.qtp_set_bodies(dev(sc.x), dev(sc.v), dev(sc.w), dev(sc.radius), dev(sc.mass))
-    ctx.qtp_set_walls(sc.planes)
-    ctx.qtp_set_params(sc.mu, sc.h, sc.delta, sc.gravity, sc.log2n)
+    base = dict(qtt_rmax=a.rmax, qtt_rmax_s=a.rmax_s, qtt_eps=a.eps, solve_mode=1,
+                solve_tol=1e-8, fgmres_restart=a.restart, fgmres_maxit=3000,
+                ns_iters=a.ns_iters, ns_iters_hot=a.ns_iters_hot)
+    ctx = make_context(binding, torch, sc,
+                       **dict(base, precision=a.precision, qtt_mode=a.qtt_mode))
     n = 1 << sc.log2n
 
-    stats = []
-    recs = []
+    stats, recs = [], []
+    g_first = None
     for i in range(a.warmup):
         rc, st = ctx.qtp_step()
-        print(f"warmup step {i}: {st.n_contacts} contacts, {st.pdip_iterations} PDIP "
-              f"its, {st.fgmres_iterations} FGMRES its, {st.ms_total:.1f} ms",
-              file=sys.stderr, flush=True)
+        if i == 0:
+            g_first = ctx.qtp_get_impulses(st.n_contacts).cpu().numpy()
+        log(f"warmup step {i}: {st.n_contacts} contacts, {st.pdip_iterations} PDIP "
+            f"its, {st.fgmres_iterations} FGMRES its, {st.ms_total:.1f} ms")
     torch.cuda.synchronize()
     ctx.qtp_profile(True)
     t0 = time.perf_counter()
@@ -126,38 +274,36 @@ def main():
         rc, st = ctx.qtp_step()
         stats.append(st)
         recs.extend(ctx.qtp_get_newton_log())
-        print(f"step {i}: {st.n_contacts} contacts, {st.pdip_iterations} PDIP its "
-              f"(converged {st.converged}), {st.fgmres_iterations} FGMRES its "
-              f"(max {st.max_fgmres}), qtt_used {st.qtt_used}, precond {st.ms_precond:.1f} ms, solves "
-              f"{st.ms_solve:.1f} ms, total {st.ms_total:.1f} ms",
-              file=sys.stderr, flush=True)
+        log(f"step {i}: {st.n_contacts} contacts, {st.pdip_iterations} PDIP its "
+            f"(converged {st.converged}), {st.fgmres_iterations} FGMRES its "
+            f"(max {st.max_fgmres}), qtt_used {st.qtt_used}, precond "
+            f"{st.ms_precond:.1f} ms, solves {st.ms_solve:.1f} ms, total "
+            f"{st.ms_total:.1f} ms")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / a.steps
-    # dominant Newton-step kernel: the BSR3 sparse product
-    sp_ms, sp_n = ctx.qtp_get_kernel_time("bsr_spmv")
-    qa_ms, qa_n = ctx.qtp_get_kernel_time("qtt_apply")
-    cg_ms, cg_n = ctx.qtp_get_kernel_time("cgs2")
+    kernels = {}
+    for name in ("bsr_spmv", "arnoldi_next", "arnoldi_dots", "arnoldi_orth",
+                 "qtt_apply"):
+        ms, cnt = ctx.qtp_get_kernel_time(name)
+        kernels[name] = {"ms_avg": ms / max(cnt, 1), "launches": cnt}
     ctx.qtp_profile(False)
     try:
         ranks_x = ctx.qtp_get_qtt_ranks(1)
         ranks_s = ctx.qtp_get_qtt_ranks(0)
     except binding.QtpError:  # block-Jacobi only: no QTT was built
         ranks_x = ranks_s = None
-    pst = ctx.qtp_get_precond_stats()
     _, _, valN, _ = ctx.qtp_get_qp(sc.log2n)
     nnzb = valN.numel() // 9
     ctx.close()
 
-    solve_ms = float(np.median([r.solve_ms for r in recs]))
     its = np.array([r.fgmres_iterations for r in recs])
     sms = np.array([r.solve_ms for r in recs])
-    print("newton solves: iterations " + " ".join(str(int(i)) for i in its),
-          file=sys.stderr, flush=True)
-    fg = [s.fgmres_iterations / max(s.pdip_iterations, 1) for s in stats]
-    sp_avg = sp_ms / max(sp_n, 1)
-    sp_bytes = spmv_bytes(nnzb, n)
-    achieved = sp_bytes / (sp_avg * 1e-3) / 1e9 if sp_n else None
+    log("newton solves: iterations " + " ".join(str(int(i)) for i in its))
+    # dominant Newton-step kernel: the BSR3 sparse product
+    sp = kernels["bsr_spmv"]
+    sp["bytes"] = spmv_bytes(nnzb, n)
+    achieved = sp["bytes"] / (sp["ms_avg"] * 1e-3) / 1e9 if sp["launches"] else None
     out = {
         "metric": "Newton-step solve ms & PDIP time-step ms at 2^20 unknowns, "
                   "1e-8 residual",
@@ -175,28 +321,25 @@ def main():
         "config": {
             "workload": f"{a.scene}: {sc.M} spheres, 2^{sc.log2n} unknowns, "
                         f"mu {sc.mu}, h {sc.h}",
-            "qtt_cores": a.precision, "qtt_eps": a.eps, "qtt_rmax": a.rmax,
-            "qtt_rmax_s": a.rmax_s, "fgmres": f"FGMRES({a.restart}) to 1e-8",
-            "pdip_gap_tol": 1e-8, "qtt_mode": a.qtt_mode,
+            "qtt_mode": a.qtt_mode, "qtt_cores": a.precision, "qtt_eps": a.eps,
+            "qtt_rmax": a.rmax, "qtt_rmax_s": a.rmax_s,
+            "fgmres": f"FGMRES({a.restart}) to 1e-8", "pdip_gap_tol": 1e-8,
         },
-        "qtt_used": [s.qtt_used for s in stats],
-        "trial_iterations": {"qtt": [s.qtt_trial_iterations for s in stats],
-                             "block_jacobi": [s.plain_trial_iterations for s in stats]},
-        "newton_solve_ms": solve_ms,
-        "qtt_ranks_last": {"X": ranks_x, "S": ranks_s,
-                           "ns_iterations": pst.ns_iterations,
-                           "probe_residual": pst.probe_residual},
+        "newton_solve_ms": float(np.median(sms)),
         "newton_solves": {
             "count": int(len(recs)),
-            "ms": {"median": solve_ms, "p90": float(np.percentile(sms, 90)),
+            "ms": {"median": float(np.median(sms)), "p90": float(np.percentile(sms, 90)),
                    "max": float(sms.max()), "mean": float(sms.mean())},
             "fgmres_iterations": {"median": float(np.median(its)),
                                   "p90": float(np.percentile(its, 90)),
                                   "max": int(its.max()), "mean": float(its.mean())},
             "max_rel_residual": float(max(r.rel_residual for r in recs)),
         },
+        "qtt_used": [s.qtt_used for s in stats],
+        "trial_iterations": {"qtt": [s.qtt_trial_iterations for s in stats],
+                             "block_jacobi": [s.plain_trial_iterations for s in stats]},
+        "qtt_ranks_last": {"X": ranks_x, "S": ranks_s},
         "pdip_iterations": [s.pdip_iterations for s in stats],
-        "fgmres_iterations_per_newton": fg,
         "contacts": [s.n_contacts for s in stats],
         "ms_split": {
             "detect": float(np.mean([s.ms_detect for s in stats])),
@@ -206,20 +349,32 @@ def main():
             "pdip_total": float(np.mean([s.ms_pdip for s in stats])),
             "integrate": float(np.mean([s.ms_integrate for s in stats])),
         },
-        "kernels": {
-            "bsr_spmv": {"ms_avg": sp_avg, "launches": sp_n, "bytes": sp_bytes},
-            "qtt_apply": {"ms_avg": qa_ms / max(qa_n, 1), "launches": qa_n},
-            "cgs2": {"ms_avg": cg_ms / max(cg_n, 1), "launches": cg_n},
-        },
+        "kernels": kernels,
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
             "traffic": None, "kernel": "bsr_spmv",
         },
+        "forms": None,
         "cpu_baseline": None,
     }
+    if not a.no_forms:
+        forms = {}
+        f64, g64 = qtt_form(binding, torch, sc, base, "f64")
+        forms["qtt_f64"] = f64
+        for prec in ("f32", "bf16"):
+            f, g = qtt_form(binding, torch, sc, base, prec)
+            f["impulse_rel_err_vs_qtt_f64"] = rel_err(g, g64)
+            forms[f"qtt_{prec}"] = f
+        f, g = simple_form(binding, torch, sc, dict(base, qtt_mode=0), "block_jacobi")
+        f["impulse_rel_err_vs_qtt_f64"] = rel_err(g, g64)
+        forms["block_jacobi"] = f
+        if g_first is not None:
+            forms["headline_first_step_impulse_rel_err_vs_qtt_f64"] = rel_err(g_first, g64)
+        forms["mlp_warm_start"] = mlp_form(binding, torch, sc, dict(base, qtt_mode=0))
+        out["forms"] = forms
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(a.precision)
+        out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))
 
 

@@ -281,6 +281,12 @@ int64_t qtp_mlp_param_count(void);
  * follows qtp_detect and qtp_assemble. */
 qtp_status qtp_mlp_features(qtp_ctx ctx, float* X);
 
+/* Training targets [nc][3] FP32 (device) of the last PDIP solve's impulses in
+ * scaled units: log(gamma_n) and gamma_t / (mu gamma_n) projected into the
+ * unit disc, the inverse of the warm start's output map.  Valid after
+ * qtp_pdip_solve (or qtp_step, which leaves the contacts of its solve). */
+qtp_status qtp_mlp_targets(qtp_ctx ctx, float* Y);
+
 /* Sets / gets the parameters (device, qtp_mlp_param_count floats); setting
  * resets the Adam moments. */
 qtp_status qtp_mlp_set_params(qtp_ctx ctx, const float* params);

@@ -116,6 +116,7 @@ SIGNATURES = {
     "qtp_step": (_I, [_P, _P]),
     "qtp_mlp_param_count": (_I64, []),
     "qtp_mlp_features": (_I, [_P, _P]),
+    "qtp_mlp_targets": (_I, [_P, _P]),
     "qtp_mlp_set_params": (_I, [_P, _P]),
     "qtp_mlp_get_params": (_I, [_P, _P]),
     "qtp_mlp_fit_normalization": (_I, [_P, _P, _I64]),
@@ -331,6 +332,13 @@ class Context:
         X = torch.empty(nc, 11, dtype=torch.float32, device="cuda")
         self._check(self.lib.qtp_mlp_features(self.h, _ptr(X)))
         return X
+
+    def qtp_mlp_targets(self, nc):
+        """Training targets [nc][3] FP32 of the last PDIP solve."""
+        import torch
+        Y = torch.empty(nc, 3, dtype=torch.float32, device="cuda")
+        self._check(self.lib.qtp_mlp_targets(self.h, _ptr(Y)))
+        return Y
 
     def qtp_mlp_set_params(self, params):
         return self._check(self.lib.qtp_mlp_set_params(self.h, _ptr(params)))

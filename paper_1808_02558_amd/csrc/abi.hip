@@ -504,6 +504,14 @@ qtp_status qtp_mlp_features(qtp_ctx ctx, float* X) {
   });
 }
 
+qtp_status qtp_mlp_targets(qtp_ctx ctx, float* Y) {
+  return guarded(ctx, [&](Ctx& c) {
+    QTP_REQUIRE(Y, QTP_E_ARG, "null pointer");
+    qtp::mlp_targets(c, Y);
+    return QTP_OK;
+  });
+}
+
 qtp_status qtp_mlp_set_params(qtp_ctx ctx, const float* params) {
   return guarded(ctx, [&](Ctx& c) {
     QTP_REQUIRE(params, QTP_E_ARG, "null pointer");

@@ -285,6 +285,7 @@ int detect_contacts(Ctx& c) {
   const hipStream_t s = c.stream;
   const int M = sc.M;
   QTP_REQUIRE(M >= 1, QTP_E_STATE, "no bodies set");
+  c.pd.have_gamma = false;  // impulses belong to the previous contact set
   // bounding box and the largest radius
   const int nb = std::min(256, div_up(M, kT));
   c.tmp1.ensure(sizeof(double) * 7 * nb);

@@ -18,6 +18,7 @@ struct Mlp {
 
 int64_t mlp_param_count();
 void mlp_features(Ctx& c, float* X);
+void mlp_targets(Ctx& c, float* Y);
 void mlp_set_params(Ctx& c, const float* params);
 void mlp_fit_normalisation(Ctx& c, const float* X, int64_t n);
 void mlp_get_normalisation(Ctx& c, float* mean_host, float* istd_host);

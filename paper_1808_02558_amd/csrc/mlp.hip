@@ -262,6 +262,21 @@ __global__ void warm_start_kernel(int nc, double mu, double t0,
   lam[nc + i] = 1.0 / (t0 * gn);
 }
 
+// training targets of the solved impulses (scaled units): log gamma_n and the
+// friction ratio gamma_t / (mu gamma_n) projected into the unit disc
+__global__ void targets_kernel(int nc, double mu, const int32_t* __restrict__ slot,
+                               const double* __restrict__ gamma, float* __restrict__ Y) {
+  const int i = blockIdx.x * kT + threadIdx.x;
+  if (i >= nc) return;
+  const int64_t u = 3 * (int64_t)slot[i];
+  const double gn = gamma[u];
+  const double q1 = gamma[u + 1] / (mu * gn), q2 = gamma[u + 2] / (mu * gn);
+  const double nq = fmax(1.0, sqrt(q1 * q1 + q2 * q2));
+  Y[3 * (int64_t)i] = (float)log(fmax(gn, 1e-6));
+  Y[3 * (int64_t)i + 1] = (float)(q1 / nq);
+  Y[3 * (int64_t)i + 2] = (float)(q2 / nq);
+}
+
 void sgemm(hipStream_t s, int transA, int transB, int M, int N, int K, const float* A,
            int lda, const float* B, int ldb, float* C, int ldc, int epi,
            const float* bias, const float* H, DevBuf* ws) {
@@ -492,6 +507,16 @@ double mlp_train_step(Ctx& c, const float* X, const float* Y, int B, double lr) 
   QTP_CHECK_LAUNCH();
   QTP_HIP(hipStreamSynchronize(c.stream));
   return loss;
+}
+
+void mlp_targets(Ctx& c, float* Y) {
+  QTP_REQUIRE(c.pd.have_gamma, QTP_E_STATE, "solve the PDIP before computing targets");
+  const int nc = c.ct.nc;
+  if (nc == 0) return;
+  targets_kernel<<<div_up(nc, kT), kT, 0, c.stream>>>(
+      nc, c.scene.mu, c.ct.slot.as<int32_t>(), c.pd.gamma.as<double>(), Y);
+  QTP_CHECK_LAUNCH();
+  QTP_HIP(hipStreamSynchronize(c.stream));
 }
 
 // features -> prediction -> PDIP start (gamma, lambda) on the padded layout

@@ -533,13 +533,14 @@ int pdip_solve(Ctx& c, qtp_step_stats* st) {
     }
     if (rc == QTP_OK) return rc;
     const int wit = st->pdip_iterations;
-    const double wpre = st->ms_precond, wsol = st->ms_solve;
+    const double wpre = st->ms_precond, wsol = st->ms_solve, wpd = st->ms_pdip;
     const int wfg = st->fgmres_iterations;
     rc = pdip_run(c, st, false);
     st->warm_fallback = 1;
     st->warm_iterations = wit;
     st->ms_precond += wpre;
     st->ms_solve += wsol;
+    st->ms_pdip += wpd;  // the failed warm run is part of the cost
     st->fgmres_iterations += wfg;
     return rc;
   }

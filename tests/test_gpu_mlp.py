@@ -119,9 +119,7 @@ def collect(torch, ctx, sc, steps):
         Xs.append(ctx.qtp_mlp_features(nc))
         rc, st = ctx.qtp_pdip_solve()
         assert rc == 0
-        g = ctx.qtp_get_impulses(nc).cpu().numpy()
-        gbar = sc.mass.mean() * np.linalg.norm(sc.gravity) * sc.h
-        Ys.append(dev(torch, mlp.targets(g.reshape(-1) / gbar, sc.mu), torch.float32))
+        Ys.append(ctx.qtp_mlp_targets(nc))
         ctx.qtp_integrate()
     return torch.cat(Xs), torch.cat(Ys)
 

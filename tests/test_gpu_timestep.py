@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import scenes
-from oracle import assembly, contacts, pdip
+from oracle import assembly, contacts, pdip, mlp
 from tests import cases, helpers
 
 pytestmark = pytest.mark.gpu
@@ -94,6 +94,7 @@ def test_pdip_step_matches_oracle(torch, name):
         ctx.qtp_assemble()
         rc, st = ctx.qtp_pdip_solve()
         g = ctx.qtp_get_impulses(c.nc).cpu().numpy().reshape(-1)
+        Y = ctx.qtp_mlp_targets(c.nc).cpu().numpy().astype(np.float64)
         ctx.qtp_integrate()
         x, v, w = (t.cpu().numpy() for t in ctx.qtp_get_state(sc.M))
     finally:
@@ -107,6 +108,12 @@ def test_pdip_step_matches_oracle(torch, name):
     vscale = np.linalg.norm(sc.gravity) * sc.h
     assert np.abs(v - v_o).max() <= 1e-6 * vscale
     assert np.abs(x - x_o).max() <= 1e-6 * vscale * sc.h
+    # training targets of the warm start, from the oracle's impulses
+    gbar = sc.mass.mean() * np.linalg.norm(sc.gravity) * sc.h
+    Yo = mlp.targets(gamma_o / gbar, sc.mu)
+    big = gamma_o.reshape(-1, 3)[:, 0] >= 1e-3 * gbar
+    assert np.isfinite(Y).all()
+    assert np.abs(Y - Yo)[big].max() <= 1e-4
 
 
 @pytest.mark.parametrize("theta,mu", [(0.0, 0.5), (0.3, 0.5), (math.pi / 6, 0.05)])
