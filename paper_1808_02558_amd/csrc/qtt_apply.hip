@@ -15,6 +15,8 @@
 // read with coalesced vector loads (consecutive threads, consecutive J).
 #include <hip/hip_bf16.h>
 
+#include <algorithm>
+
 #include "ops.h"
 
 namespace qtp {
@@ -188,6 +190,87 @@ __global__ __launch_bounds__(kThreads) void qtt_fused_kernel(
   }
 }
 
+// ---------------------------------------------------------------------------
+// Register-resident fusion for small ranks.  One thread owns one column pair
+// (I, J'') of a pass over M levels and keeps its whole fibre
+// Z[I][alpha][jj (M bits)][J''] (alpha < R) in registers: each level replaces
+// the leading remaining column bit j by the row bit i at the same position,
+// so no data moves between threads and no barrier is needed.  The core
+// entries are the same for every thread and are read through the scalar
+// cache; the fibres are read and written with loads and stores that are
+// coalesced over consecutive J''.
+// ---------------------------------------------------------------------------
+template <int R, int M, class CT, class IT, class OT, class AT>
+__global__ __launch_bounds__(kThreads) void qtt_reg_kernel(
+    const CT* __restrict__ cores, FusePlan P, int log2J, int64_t nthreads,
+    const IT* __restrict__ in, OT* __restrict__ out) {
+  const int64_t tid = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (tid >= nthreads) return;
+  const int64_t Jtot = (int64_t)1 << log2J;
+  const int64_t I = tid >> log2J;
+  const int64_t J = tid & (Jtot - 1);
+  constexpr int F = 1 << M;
+  AT v[R][F];
+  const int r0 = P.ra[0];
+#pragma unroll
+  for (int a = 0; a < R; ++a) {
+    if (a < r0) {
+#pragma unroll
+      for (int p = 0; p < F; ++p)
+        v[a][p] = (AT)in[(((I * r0 + a) << M) + p) * Jtot + J];
+    }
+  }
+#pragma unroll
+  for (int l = 0; l < M; ++l) {
+    const int ra = P.ra[l], rb = P.ra[l + 1];
+    const CT* G = cores + P.coff[l];
+    const int sh = M - 1 - l;  // position of this level's bit in the fibre
+#pragma unroll
+    for (int g = 0; g < F / 2; ++g) {
+      const int p0 = ((g >> sh) << (sh + 1)) | (g & ((1 << sh) - 1));
+      const int p1 = p0 | (1 << sh);
+      AT t0[R], t1[R];
+#pragma unroll
+      for (int b = 0; b < R; ++b) {
+        t0[b] = AT(0);
+        t1[b] = AT(0);
+      }
+#pragma unroll
+      for (int a = 0; a < R; ++a) {
+        if (a < ra) {
+          const AT x0 = v[a][p0], x1 = v[a][p1];
+          const int64_t c00 = (int64_t)(a * 4) * rb;  // (a, i = 0, j = 0)
+#pragma unroll
+          for (int b = 0; b < R; ++b) {
+            if (b < rb) {
+              t0[b] += CoreLoad<CT>::get(G, c00 + b) * x0 +
+                       CoreLoad<CT>::get(G, c00 + rb + b) * x1;
+              t1[b] += CoreLoad<CT>::get(G, c00 + 2 * rb + b) * x0 +
+                       CoreLoad<CT>::get(G, c00 + 3 * rb + b) * x1;
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int b = 0; b < R; ++b) {
+        if (b < rb) {
+          v[b][p0] = t0[b];
+          v[b][p1] = t1[b];
+        }
+      }
+    }
+  }
+  const int rm = P.ra[M];
+#pragma unroll
+  for (int b = 0; b < R; ++b) {
+    if (b < rm) {
+#pragma unroll
+      for (int p = 0; p < F; ++p)
+        out[(((I << M) + p) * rm + b) * Jtot + J] = (OT)v[b][p];
+    }
+  }
+}
+
 template <class CT, class IT, class OT, class AT>
 void launch_fused(hipStream_t s, const CT* cores, const FusePlan& P, int d, int k0,
                   int log2T, const IT* in, OT* out, size_t lds) {
@@ -199,7 +282,71 @@ void launch_fused(hipStream_t s, const CT* cores, const FusePlan& P, int d, int 
   QTP_CHECK_LAUNCH();
 }
 
-// Greedy pass plan: the longest run of levels whose slab fits the LDS budget.
+template <int R, int M, class CT, class IT, class OT, class AT>
+void launch_reg(hipStream_t s, const CT* cores, const FusePlan& P, int d, int k0,
+                const IT* in, OT* out) {
+  const int log2J = d - (k0 + M - 1);
+  const int64_t nthreads = (int64_t)1 << (d - M);  // 2^{k0-1} prefixes x 2^{log2J}
+  qtt_reg_kernel<R, M, CT, IT, OT, AT><<<div_up(nthreads, kThreads), kThreads, 0, s>>>(
+      cores, P, log2J, nthreads, in, out);
+  QTP_CHECK_LAUNCH();
+}
+
+// Register pass over M levels whose ranks are all <= R (R * 2^M values per
+// thread; FP64 keeps R <= 16).
+template <class CT, class IT, class OT, class AT>
+bool try_reg_pass(hipStream_t s, const CT* cores, const FusePlan& P, int d, int k0,
+                  int R, const IT* in, OT* out) {
+  const int M = P.m;
+  const bool wide = sizeof(AT) == 8;
+#define QTP_REG(RR, MM)                                                       \
+  if (R <= RR && M == MM) {                                                   \
+    launch_reg<RR, MM, CT, IT, OT, AT>(s, cores, P, d, k0, in, out);          \
+    return true;                                                              \
+  }
+  if (wide) {
+    QTP_REG(4, 3)
+    QTP_REG(8, 2)
+    QTP_REG(16, 1)
+  } else {
+    QTP_REG(4, 4)
+    QTP_REG(8, 3)
+    QTP_REG(16, 2)
+    QTP_REG(16, 1)
+    if (sizeof(CT) != 2) {
+      QTP_REG(32, 1)
+    }
+  }
+#undef QTP_REG
+  return false;
+}
+
+// Levels a register pass can take from level k0 (1-based) on: the largest M
+// whose window of ranks fits the register budget while the pass still has
+// at least 2^17 threads (512 workgroups), or 0 when even one level is too
+// wide.
+int reg_levels(int d, const int32_t* ranks, int k0, bool wide, bool bf16, int* R_out) {
+  const int cap_threads = d > 17 ? d - 17 : 0;  // M <= d - 17 keeps 2^17 threads
+  for (int M = std::min(4, d - k0 + 1); M >= 1; --M) {
+    if (M > 1 && M > cap_threads) continue;
+    int rm = 1;
+    for (int l = 0; l <= M; ++l) rm = std::max<int>(rm, ranks[k0 - 1 + l]);
+    int R = 4;
+    while (R < rm) R <<= 1;
+    // register budget: R * 2^M values plus 2R accumulators (FP64 one step
+    // narrower so that no variant needs more than ~160 VGPRs)
+    const int maxR = wide ? (M == 4 ? 0 : M == 3 ? 4 : M == 2 ? 8 : 16)
+                          : (M == 4 ? 4 : M == 3 ? 8 : M == 2 ? 16 : (bf16 ? 16 : 32));
+    if (R <= maxR) {
+      *R_out = R;
+      return M;
+    }
+  }
+  return 0;
+}
+
+// Greedy pass plan: register passes while the ranks are small, otherwise the
+// longest run of levels whose slab fits the LDS budget.
 template <class CT, class IT>
 void apply_fused(hipStream_t s, int d, const int32_t* ranks, const CT* cores,
                  const double* x, double* y, void* work) {
@@ -213,6 +360,29 @@ void apply_fused(hipStream_t s, int d, const int32_t* ranks, const CT* cores,
   int k0 = 1, cur = 0;
   bool first = true;
   while (k0 <= d) {
+    int R = 0;
+    const int mr = reg_levels(d, ranks, k0, sizeof(AT) == 8, sizeof(CT) == 2, &R);
+    if (mr > 0) {
+      FusePlan P{};
+      P.m = mr;
+      for (int l = 0; l <= mr; ++l) P.ra[l] = ranks[k0 - 1 + l];
+      for (int l = 0; l < mr; ++l) P.coff[l] = off[k0 - 1 + l];
+      const bool last = k0 + mr - 1 == d;
+      bool ok;
+      if (first && last)
+        ok = try_reg_pass<CT, double, double, AT>(s, cores, P, d, k0, R, x, y);
+      else if (first)
+        ok = try_reg_pass<CT, double, IT, AT>(s, cores, P, d, k0, R, x, buf[cur]);
+      else if (last)
+        ok = try_reg_pass<CT, IT, double, AT>(s, cores, P, d, k0, R, buf[cur ^ 1], y);
+      else
+        ok = try_reg_pass<CT, IT, IT, AT>(s, cores, P, d, k0, R, buf[cur ^ 1], buf[cur]);
+      QTP_REQUIRE(ok, -1, "QTT apply: no register kernel for this pass");
+      first = false;
+      cur ^= 1;
+      k0 += mr;
+      continue;
+    }
     int m = std::min(kMaxFuse, d - k0 + 1), log2T = 0;
     for (; m >= 1; --m) {
       const int log2J = d - (k0 + m - 1);
