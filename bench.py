@@ -151,10 +151,11 @@ def simple_form(binding, torch, sc, cfg, label):
     return step_summary(st), g
 
 
-def mlp_form(binding, torch, sc, base, train_steps=2, epochs=6, batch=4096, lr=1e-3):
+def mlp_form(binding, torch, sc, base, train_steps=2, epochs=12, batch=4096, lr=1e-3):
     """Learned warm start: train the network on the solved impulses of the
     first time steps (the library's forward, backward and Adam kernels), then
-    solve the next time step from its prediction and from the cold start."""
+    solve the next time step cold and from the prediction, for several
+    centring parameters t0 and floors on the predicted normal impulse."""
     import numpy as np
 
     import scenes
@@ -190,32 +191,52 @@ def mlp_form(binding, torch, sc, base, train_steps=2, epochs=6, batch=4096, lr=1
                 nsteps += 1
         torch.cuda.synchronize()
         train_ms = (time.perf_counter() - t0) * 1e3
+        # held-out step: cold first (also gives the held-out targets)
         nc = ctx.qtp_detect()
         ctx.qtp_assemble()
-        ctx.qtp_set_config(warm_start=2)
-        rc_w, warm = ctx.qtp_pdip_solve()
-        gw = ctx.qtp_get_impulses(nc).cpu().numpy()
-        ctx.qtp_set_config(warm_start=0)
+        Xh = ctx.qtp_mlp_features(nc)
         rc_c, cold = ctx.qtp_pdip_solve()
         gc = ctx.qtp_get_impulses(nc).cpu().numpy()
+        Yh = ctx.qtp_mlp_targets(nc)
+        Ph = ctx.qtp_mlp_forward(Xh)
+        err = (Ph - Yh).double()
+        loaded = Yh[:, 0] > float(np.log(1e-3))
+        held = {"mse": float((err ** 2).mean()),
+                "rms_log_gn_loaded": float((err[loaded, 0] ** 2).mean().sqrt()),
+                "rms_log_gn_unloaded": float((err[~loaded, 0] ** 2).mean().sqrt()),
+                "loaded_fraction": float(loaded.double().mean())}
+        trials = []
+        for t0w in (1.0, 10.0, 100.0):
+            for floor in (0.0, 1e-3, 1e-2, 1e-1):
+                ctx.qtp_set_config(warm_start=2, warm_t0=t0w, warm_floor=floor)
+                rc_w, warm = ctx.qtp_pdip_solve()
+                gw = ctx.qtp_get_impulses(nc).cpu().numpy()
+                trials.append({"t0": t0w, "floor": floor,
+                               "pdip_iterations": (warm.warm_iterations
+                                                   if warm.warm_fallback
+                                                   else warm.pdip_iterations),
+                               "fallback": bool(warm.warm_fallback),
+                               "ms": warm.ms_pdip,
+                               "impulse_rel_diff_vs_cold": rel_err(gw, gc)})
+        ctx.qtp_set_config(warm_start=0)
     finally:
         ctx.close()
-    log(f"form mlp: warm {warm.pdip_iterations} PDIP its {warm.ms_pdip:.1f} ms "
-        f"(fallback {warm.warm_fallback}), cold {cold.pdip_iterations} its "
-        f"{cold.ms_pdip:.1f} ms; loss {first:.4f} -> {last:.4f}")
+    best = min(trials, key=lambda t: t["ms"])
+    log(f"form mlp: cold {cold.pdip_iterations} PDIP its {cold.ms_pdip:.1f} ms; best "
+        f"warm t0 {best['t0']} floor {best['floor']}: {best['pdip_iterations']} its "
+        f"{best['ms']:.1f} ms (fallback {best['fallback']}); loss {first:.4f} -> "
+        f"{last:.4f}, held-out mse {held['mse']:.4f}")
     return {
         "training": {"rows": int(rows), "steps_of_data": train_steps, "epochs": epochs,
                      "adam_steps": nsteps, "batch": batch, "lr": lr,
                      "loss_first": first, "loss_last": last, "ms": train_ms},
         "held_out_step": {
-            "warm": {"pdip_iterations": warm.pdip_iterations,
-                     "fgmres_iterations": warm.fgmres_iterations, "ms": warm.ms_pdip,
-                     "fallback": bool(warm.warm_fallback),
-                     "converged": bool(warm.converged)},
+            "prediction": held,
             "cold": {"pdip_iterations": cold.pdip_iterations,
                      "fgmres_iterations": cold.fgmres_iterations, "ms": cold.ms_pdip,
                      "converged": bool(cold.converged)},
-            "impulse_rel_diff_warm_vs_cold": rel_err(gw, gc)},
+            "warm_trials": trials,
+            "best_warm": best},
     }
 
 

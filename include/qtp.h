@@ -83,6 +83,9 @@ typedef struct {
                            1 QTT inverse on every Newton step,
                            2 auto: the first Newton step of a time step is
                              solved with both, the faster is kept */
+  double warm_floor;    /* learned start: lower bound on the predicted normal
+                           impulse in scaled units (keeps the start away from
+                           the cone's boundary) */
 } qtp_config;
 
 /* Fills a config with the defaults: FP64, eps 1e-2, rmax 32, rmax_s 16,

@@ -47,6 +47,7 @@ class Config(ctypes.Structure):
         ("seed", ctypes.c_uint64),
         ("warm_t0", ctypes.c_double),
         ("qtt_mode", ctypes.c_int),
+        ("warm_floor", ctypes.c_double),
     ]
 
 

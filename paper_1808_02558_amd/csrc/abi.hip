@@ -2,6 +2,7 @@
 // translation of internal errors into qtp_status codes.  Nothing here
 // computes; every step runs in the kernels of the other files.
 #include <chrono>
+#include <cmath>
 #include <cstring>
 
 #include "context.h"
@@ -81,6 +82,8 @@ void qtp::Ctx::check_cfg() {
   QTP_REQUIRE(cfg.qtt_mode >= 0 && cfg.qtt_mode <= 2, QTP_E_ARG, "qtt_mode out of [0,2]");
   QTP_REQUIRE(cfg.warm_start == 0 || cfg.warm_start == 2, QTP_E_ARG,
               "warm_start must be 0 or 2");
+  QTP_REQUIRE(cfg.warm_floor >= 0.0 && std::isfinite(cfg.warm_floor), QTP_E_ARG,
+              "warm_floor must be finite and >= 0");
 }
 
 extern "C" {
@@ -104,6 +107,7 @@ void qtp_config_default(qtp_config* cfg) {
   cfg->warm_start = 0;
   cfg->seed = 0;
   cfg->warm_t0 = 100.0;
+  cfg->warm_floor = 0.0;
   cfg->qtt_mode = 2;
 }
 

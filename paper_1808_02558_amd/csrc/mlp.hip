@@ -242,14 +242,14 @@ __global__ void adam_kernel(int64_t n, float* __restrict__ p, const float* __res
 
 // predicted impulses into the PDIP start (scaled units), multipliers on the
 // central path of t0
-__global__ void warm_start_kernel(int nc, double mu, double t0,
+__global__ void warm_start_kernel(int nc, double mu, double t0, double floor_n,
                                   const int32_t* __restrict__ slot,
                                   const float* __restrict__ P,
                                   double* __restrict__ gamma, double* __restrict__ lam) {
   const int i = blockIdx.x * kT + threadIdx.x;
   if (i >= nc) return;
   const float* p = P + 3 * (int64_t)i;
-  double gn = exp(fmin(fmax((double)p[0], -30.0), 30.0));
+  double gn = fmax(exp(fmin(fmax((double)p[0], -30.0), 30.0)), floor_n);
   double q1 = p[1], q2 = p[2];
   const double nq = fmax(1.0, sqrt(q1 * q1 + q2 * q2));
   const double g1 = 0.9 * mu * gn * q1 / nq, g2 = 0.9 * mu * gn * q2 / nq;
@@ -528,7 +528,8 @@ void mlp_warm_start(Ctx& c, double t0, double* gamma, double* lam) {
   mlp_features(c, m.feat.as<float>());
   mlp_forward(c, m.feat.as<float>(), nc, m.p.as<float>());
   warm_start_kernel<<<div_up(nc, kT), kT, 0, c.stream>>>(
-      nc, c.scene.mu, t0, c.ct.slot.as<int32_t>(), m.p.as<float>(), gamma, lam);
+      nc, c.scene.mu, t0, c.cfg.warm_floor, c.ct.slot.as<int32_t>(), m.p.as<float>(),
+      gamma, lam);
   QTP_CHECK_LAUNCH();
 }
 

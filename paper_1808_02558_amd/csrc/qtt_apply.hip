@@ -204,20 +204,47 @@ template <int R, int M, class CT, class IT, class OT, class AT>
 __global__ __launch_bounds__(kThreads) void qtt_reg_kernel(
     const CT* __restrict__ cores, FusePlan P, int log2J, int64_t nthreads,
     const IT* __restrict__ in, OT* __restrict__ out) {
-  const int64_t tid = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (tid >= nthreads) return;
+  // With fewer than 16 trailing indices the fibres of one workgroup form one
+  // contiguous run of the input (and of the output): it is staged through
+  // LDS with coalesced loads and stores instead of strided per-thread ones.
+  extern __shared__ unsigned char qtt_reg_smem[];
+  AT* stage = reinterpret_cast<AT*>(qtt_reg_smem);
+  const bool staged = log2J < 4;
+  const int64_t tid0 = (int64_t)blockIdx.x * kThreads;
+  const int64_t tid = tid0 + threadIdx.x;
+  const int cnt = (int)min<int64_t>(kThreads, nthreads - tid0);
+  const bool live = threadIdx.x < cnt;
   const int64_t Jtot = (int64_t)1 << log2J;
   const int64_t I = tid >> log2J;
   const int64_t J = tid & (Jtot - 1);
+  const int64_t Il = (int64_t)threadIdx.x >> log2J;  // prefix within the block
   constexpr int F = 1 << M;
   AT v[R][F];
   const int r0 = P.ra[0];
+  if (staged) {
+    const int64_t n_in = (int64_t)cnt * r0 * F;
+    const IT* src = in + tid0 * r0 * F;
+    for (int64_t e = threadIdx.x; e < n_in; e += kThreads) stage[e] = (AT)src[e];
+    __syncthreads();
+    if (live) {
 #pragma unroll
-  for (int a = 0; a < R; ++a) {
-    if (a < r0) {
+      for (int a = 0; a < R; ++a) {
+        if (a < r0) {
 #pragma unroll
-      for (int p = 0; p < F; ++p)
-        v[a][p] = (AT)in[(((I * r0 + a) << M) + p) * Jtot + J];
+          for (int p = 0; p < F; ++p)
+            v[a][p] = stage[(((Il * r0 + a) << M) + p) * Jtot + J];
+        }
+      }
+    }
+    __syncthreads();
+  } else if (live) {
+#pragma unroll
+    for (int a = 0; a < R; ++a) {
+      if (a < r0) {
+#pragma unroll
+        for (int p = 0; p < F; ++p)
+          v[a][p] = (AT)in[(((I * r0 + a) << M) + p) * Jtot + J];
+      }
     }
   }
 #pragma unroll
@@ -261,12 +288,29 @@ __global__ __launch_bounds__(kThreads) void qtt_reg_kernel(
     }
   }
   const int rm = P.ra[M];
+  if (staged) {
+    if (live) {
 #pragma unroll
-  for (int b = 0; b < R; ++b) {
-    if (b < rm) {
+      for (int b = 0; b < R; ++b) {
+        if (b < rm) {
 #pragma unroll
-      for (int p = 0; p < F; ++p)
-        out[(((I << M) + p) * rm + b) * Jtot + J] = (OT)v[b][p];
+          for (int p = 0; p < F; ++p)
+            stage[(((Il << M) + p) * rm + b) * Jtot + J] = v[b][p];
+        }
+      }
+    }
+    __syncthreads();
+    const int64_t n_out = (int64_t)cnt * rm * F;
+    OT* dst = out + tid0 * rm * F;
+    for (int64_t e = threadIdx.x; e < n_out; e += kThreads) dst[e] = (OT)stage[e];
+  } else if (live) {
+#pragma unroll
+    for (int b = 0; b < R; ++b) {
+      if (b < rm) {
+#pragma unroll
+        for (int p = 0; p < F; ++p)
+          out[(((I << M) + p) * rm + b) * Jtot + J] = (OT)v[b][p];
+      }
     }
   }
 }
@@ -287,7 +331,8 @@ void launch_reg(hipStream_t s, const CT* cores, const FusePlan& P, int d, int k0
                 const IT* in, OT* out) {
   const int log2J = d - (k0 + M - 1);
   const int64_t nthreads = (int64_t)1 << (d - M);  // 2^{k0-1} prefixes x 2^{log2J}
-  qtt_reg_kernel<R, M, CT, IT, OT, AT><<<div_up(nthreads, kThreads), kThreads, 0, s>>>(
+  const size_t lds = log2J < 4 ? sizeof(AT) * kThreads * R * (1 << M) : 0;
+  qtt_reg_kernel<R, M, CT, IT, OT, AT><<<div_up(nthreads, kThreads), kThreads, lds, s>>>(
       cores, P, log2J, nthreads, in, out);
   QTP_CHECK_LAUNCH();
 }
@@ -306,12 +351,20 @@ bool try_reg_pass(hipStream_t s, const CT* cores, const FusePlan& P, int d, int 
   }
   if (wide) {
     QTP_REG(4, 3)
+    QTP_REG(4, 2)
     QTP_REG(8, 2)
+    QTP_REG(4, 1)
+    QTP_REG(8, 1)
     QTP_REG(16, 1)
   } else {
     QTP_REG(4, 4)
+    QTP_REG(4, 3)
     QTP_REG(8, 3)
+    QTP_REG(4, 2)
+    QTP_REG(8, 2)
     QTP_REG(16, 2)
+    QTP_REG(4, 1)
+    QTP_REG(8, 1)
     QTP_REG(16, 1)
     if (sizeof(CT) != 2) {
       QTP_REG(32, 1)
@@ -323,8 +376,8 @@ bool try_reg_pass(hipStream_t s, const CT* cores, const FusePlan& P, int d, int 
 
 // Levels a register pass can take from level k0 (1-based) on: the largest M
 // whose window of ranks fits the register budget while the pass still has
-// at least 2^17 threads (512 workgroups), or 0 when even one level is too
-// wide.
+// at least 2^17 threads (512 workgroups), or 0 when no register pass fits;
+// the LDS-fused pass then takes over.
 int reg_levels(int d, const int32_t* ranks, int k0, bool wide, bool bf16, int* R_out) {
   const int cap_threads = d > 17 ? d - 17 : 0;  // M <= d - 17 keeps 2^17 threads
   for (int M = std::min(4, d - k0 + 1); M >= 1; --M) {
