@@ -33,6 +33,26 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
 
+# Hardware byte counters of the current bsr3_spmv_kernel on the hopper step
+# (two rocprofv3 --pmc passes, FETCH_SIZE then WRITE_SIZE, KiB per dispatch
+# averaged over the step), each scaled by what the same counter reads for a
+# 256 MiB device-to-device copy in the same program; the command lines are in
+# profiles/bsr3_spmv_hopper_2p20_traffic.md.  Reset to None whenever the
+# kernel changes until the passes are taken again.
+SPMV_COUNTERS = {
+    "hopper": {"fetch_kib": 132380.41, "write_kib": 8198.87,
+               "copy_fetch_kib": 131088.81, "copy_write_kib": 262144.0,
+               "copy_kib": 262144.0},
+}
+
+
+def spmv_traffic(scene):
+    c = SPMV_COUNTERS.get(scene)
+    if c is None:
+        return None
+    return 1024.0 * (c["fetch_kib"] * c["copy_kib"] / c["copy_fetch_kib"] +
+                     c["write_kib"] * c["copy_kib"] / c["copy_write_kib"])
+
 
 def spmv_bytes(nnzb, n):
     """Algorithmic bytes of one BSR3 product: values, block columns, row
@@ -257,6 +277,9 @@ def main():
     ap.add_argument("--scene", default="hopper")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="first run one plain device copy of this many MiB (the "
+                         "reference kernel for scaling hardware byte counters)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {a.gpus}); the "
@@ -272,6 +295,13 @@ def main():
     from paper_1808_02558_amd import binding
 
     torch.cuda.set_device(0)
+    if a.copy_probe_mb:
+        src = torch.ones(a.copy_probe_mb << 17, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: {a.copy_probe_mb} MiB device to device")
+        del src, dst
     sc = scenes.make_scene(a.scene)
     base = dict(qtt_rmax=a.rmax, qtt_rmax_s=a.rmax_s, qtt_eps=a.eps, solve_mode=1,
                 solve_tol=1e-8, fgmres_restart=a.restart, fgmres_maxit=3000,
@@ -374,7 +404,7 @@ def main():
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-            "traffic": None, "kernel": "bsr_spmv",
+            "traffic": spmv_traffic(a.scene), "kernel": "bsr_spmv",
         },
         "forms": None,
         "cpu_baseline": None,

@@ -12,6 +12,12 @@
 // The partial sums of the lanes with equal r are added with lane shuffles.
 // The identity rows past the last slot (at most two) are copied by the first
 // lanes of the grid.
+//
+// Workgroups are dealt to the 8 XCDs round-robin by workgroup id, and each
+// XCD has its own L2.  The id is remapped so that each XCD takes one
+// contiguous eighth of the block rows: Morton order keeps the entries of x
+// that a range of rows gathers inside a narrow range, so they stay in that
+// XCD's L2 instead of being fetched by every XCD.
 #include <algorithm>
 
 #include "ops.h"
@@ -20,6 +26,15 @@ namespace qtp {
 namespace {
 
 constexpr int kBlock = 256;  // threads per workgroup
+constexpr int kXcds = 8;
+
+// Bijection from the hardware workgroup id to a logical block such that the
+// workgroups of XCD k (ids = k mod 8) cover one contiguous range of blocks.
+__device__ inline int64_t xcd_block(int64_t w, int64_t nblk) {
+  const int64_t q = nblk / kXcds, rem = nblk % kXcds;
+  const int64_t k = w % kXcds, idx = w / kXcds;
+  return k * q + (k < rem ? k : rem) + idx;
+}
 
 template <int G>
 __global__ __launch_bounds__(kBlock) void bsr3_spmv_kernel(
@@ -30,12 +45,25 @@ __global__ __launch_bounds__(kBlock) void bsr3_spmv_kernel(
   const int lane = threadIdx.x & (G - 1);
   const int j = lane / 3;
   const int r = lane - 3 * j;
-  const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t gid = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   const int64_t row = gid / G;
   double acc = 0.0;
   if (row < nslots && j < J) {
     const int b1 = rp[row + 1];
-    for (int b = rp[row] + j; b < b1; b += J) {
+    int b = rp[row] + j;
+    // two blocks per trip so that both blocks' loads are in flight together
+    for (; b + J < b1; b += 2 * J) {
+      const double* v0 = val + (int64_t)b * 9 + 3 * r;
+      const double* v1 = v0 + 9 * J;
+      const int c0 = col[b], c1 = col[b + J];
+      const double a0 = v0[0], a1 = v0[1], a2 = v0[2];
+      const double e0 = v1[0], e1 = v1[1], e2 = v1[2];
+      const double* x0 = x + 3 * (int64_t)c0;
+      const double* x1 = x + 3 * (int64_t)c1;
+      acc += a0 * x0[0] + a1 * x0[1] + a2 * x0[2];
+      acc += e0 * x1[0] + e1 * x1[1] + e2 * x1[2];
+    }
+    if (b < b1) {
       const double* v = val + (int64_t)b * 9 + 3 * r;
       const double* xc = x + 3 * (int64_t)col[b];
       acc += v[0] * xc[0] + v[1] * xc[1] + v[2] * xc[2];
