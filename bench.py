@@ -275,6 +275,10 @@ def main():
     ap.add_argument("--qtt-mode", type=int, default=2, choices=[0, 1, 2],
                     help="0 block-Jacobi only, 1 QTT inverse always, 2 per-step trial")
     ap.add_argument("--scene", default="hopper")
+    ap.add_argument("--slot-mode", type=int, default=0, choices=[0, 1],
+                    help="1: contacts keep their slots across time steps")
+    ap.add_argument("--warm-start", type=int, default=0, choices=[0, 1],
+                    help="1: start each PDIP from the previous step's impulses")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -307,7 +311,8 @@ def main():
                 solve_tol=1e-8, fgmres_restart=a.restart, fgmres_maxit=3000,
                 ns_iters=a.ns_iters, ns_iters_hot=a.ns_iters_hot)
     ctx = make_context(binding, torch, sc,
-                       **dict(base, precision=a.precision, qtt_mode=a.qtt_mode))
+                       **dict(base, precision=a.precision, qtt_mode=a.qtt_mode,
+                              slot_mode=a.slot_mode, warm_start=a.warm_start))
     n = 1 << sc.log2n
 
     stats, recs = [], []
@@ -326,7 +331,9 @@ def main():
         stats.append(st)
         recs.extend(ctx.qtp_get_newton_log())
         log(f"step {i}: {st.n_contacts} contacts, {st.pdip_iterations} PDIP its "
-            f"(converged {st.converged}), {st.fgmres_iterations} FGMRES its "
+            f"(converged {st.converged}, start {st.warm_started}, fallback "
+            f"{st.warm_fallback}, kept slots {st.persistent_contacts}), "
+            f"{st.fgmres_iterations} FGMRES its "
             f"(max {st.max_fgmres}), qtt_used {st.qtt_used}, precond "
             f"{st.ms_precond:.1f} ms, solves {st.ms_solve:.1f} ms, total "
             f"{st.ms_total:.1f} ms")
@@ -373,7 +380,8 @@ def main():
             "workload": f"{a.scene}: {sc.M} spheres, 2^{sc.log2n} unknowns, "
                         f"mu {sc.mu}, h {sc.h}",
             "qtt_mode": a.qtt_mode, "qtt_cores": a.precision, "qtt_eps": a.eps,
-            "qtt_rmax": a.rmax, "qtt_rmax_s": a.rmax_s,
+            "qtt_rmax": a.rmax, "qtt_rmax_s": a.rmax_s, "slot_mode": a.slot_mode,
+            "warm_start": a.warm_start,
             "fgmres": f"FGMRES({a.restart}) to 1e-8", "pdip_gap_tol": 1e-8,
         },
         "newton_solve_ms": float(np.median(sms)),

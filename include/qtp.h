@@ -76,16 +76,23 @@ typedef struct {
   double pdip_gap_tol;  /* PDIP stop: gap / m */
   double pdip_dual_tol; /* PDIP stop: |r_dual|_inf in scaled units */
   int pdip_maxit;
-  int warm_start;       /* 0 cold, 2 learned (MLP) with cold fallback */
+  int warm_start;       /* 0 cold; 1 previous step's impulses for contacts that
+                           kept their slot (slot_mode 1), cold for new ones;
+                           2 learned (MLP); 1 and 2 fall back to cold */
   uint64_t seed;
   double warm_t0;       /* central-path parameter of the learned start */
   int qtt_mode;         /* PDIP preconditioner: 0 block-Jacobi only (X = I),
                            1 QTT inverse on every Newton step,
                            2 auto: the first Newton step of a time step is
                              solved with both, the faster is kept */
-  double warm_floor;    /* learned start: lower bound on the predicted normal
-                           impulse in scaled units (keeps the start away from
-                           the cone's boundary) */
+  double warm_floor;    /* learned and previous-step starts: lower bound on
+                           the starting normal impulse in scaled units (keeps
+                           the start away from the cone's boundary) */
+  int slot_mode;        /* 0: fresh slot map every step (Morton rank order);
+                           1: contacts present in the previous step keep their
+                             slot, new ones take the next free slot at or
+                             after their fresh one, rebuilt when none is left
+                             (Sec. 3.3, re-use across time steps) */
 } qtp_config;
 
 /* Fills a config with the defaults: FP64, eps 1e-2, rmax 32, rmax_s 16,
@@ -224,9 +231,11 @@ typedef struct {
   int qtt_used;            /* Newton steps solved with the QTT inverse */
   int qtt_trial_iterations;   /* auto mode: FGMRES its of the QTT trial */
   int plain_trial_iterations; /* auto mode: FGMRES its of the X = I trial */
-  int warm_started;        /* 1 when the learned start was used */
+  int warm_started;        /* start used: 0 cold, 1 previous step, 2 learned */
   int warm_fallback;       /* 1 when it failed and the cold start ran */
   int warm_iterations;     /* PDIP iterations spent in the failed warm run */
+  int persistent_contacts; /* slot_mode 1: contacts that kept their slot */
+  int slots_rebuilt;       /* slot_mode 1: 1 when the map fell back to fresh */
 } qtp_step_stats;
 
 /* PDIP on the assembled QP (Sec. 2.4 with the Schur-complement Newton system

@@ -214,6 +214,50 @@ def detect(scene, method="auto"):
     return Contacts(a, b, phi, frame, key, M)
 
 
+def slot_map_persistent(prev_a, prev_b, prev_slot, a, b, log2n):
+    """Slots that keep persistent contacts in place (Sec. 3.3: the contact set
+    changes little between time steps, so the tree of the previous step is
+    re-used and only the changed leaves move).
+
+    prev_a, prev_b, prev_slot: the contacts of the previous step and their
+    slots (any order); a, b: the current contacts in Morton order.  A contact
+    is persistent when the same pair (a, b) was a contact before; it keeps
+    its slot.  The other contacts, in Morton order, each take the lowest free
+    slot that is at or after its slot in the fresh map, floor(q S / Nc), and
+    after the slot the previous new contact took.  When a new contact finds no
+    such slot the whole map is rebuilt fresh.
+
+    Returns (slot, persistent mask, rebuilt flag).
+    """
+    S = (1 << log2n) // 3
+    nc = len(a)
+    if nc > S:
+        raise ValueError(f"{nc} contacts exceed the {S} slots of 2^{log2n}")
+    fresh, _ = slot_map(nc, log2n)
+    old = {(int(x), int(y)): int(s) for x, y, s in zip(prev_a, prev_b, prev_slot)}
+    slot = np.full(nc, -1, np.int64)
+    persistent = np.zeros(nc, bool)
+    taken = np.zeros(S, bool)
+    for q in range(nc):
+        s_old = old.get((int(a[q]), int(b[q])))
+        if s_old is not None:
+            slot[q] = s_old
+            persistent[q] = True
+            taken[s_old] = True
+    last = -1
+    for q in range(nc):
+        if persistent[q]:
+            continue
+        s = max(int(fresh[q]), last + 1)
+        while s < S and taken[s]:
+            s += 1
+        if s >= S:
+            return fresh, np.zeros(nc, bool), True
+        slot[q] = s
+        last = s
+    return slot, persistent, False
+
+
 def slot_map(nc, log2n):
     """Slot of each contact (in Morton rank order) and the dummy mask.
 

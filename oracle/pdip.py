@@ -225,7 +225,10 @@ def pdip(N, r, mu, params=None, gamma0=None, lam0=None, solve=None,
     while True:
         f = constraints(gamma, mu)
         gap = float(-f @ lam)
-        t = p.mu_pd * m / gap
+        # B&V's rule t = mu m / eta, capped where the central point already
+        # meets the gap tolerance: further increase only worsens the
+        # conditioning of S while the dual residual is being driven down
+        t = min(p.mu_pd * m / gap, p.mu_pd / p.tol_gap)
         r_dual, r_cent = residuals(N, r, gamma, lam, mu, t)
         dual_inf = float(np.abs(r_dual).max()) if nc else 0.0
         if gap / m <= p.tol_gap and dual_inf <= p.tol_dual:

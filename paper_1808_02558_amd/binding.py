@@ -48,6 +48,7 @@ class Config(ctypes.Structure):
         ("warm_t0", ctypes.c_double),
         ("qtt_mode", ctypes.c_int),
         ("warm_floor", ctypes.c_double),
+        ("slot_mode", ctypes.c_int),
     ]
 
 
@@ -74,7 +75,8 @@ class StepStats(ctypes.Structure):
                 ("qtt_used", ctypes.c_int), ("qtt_trial_iterations", ctypes.c_int),
                 ("plain_trial_iterations", ctypes.c_int),
                 ("warm_started", ctypes.c_int), ("warm_fallback", ctypes.c_int),
-                ("warm_iterations", ctypes.c_int)]
+                ("warm_iterations", ctypes.c_int),
+                ("persistent_contacts", ctypes.c_int), ("slots_rebuilt", ctypes.c_int)]
 
 
 class NewtonRecord(ctypes.Structure):

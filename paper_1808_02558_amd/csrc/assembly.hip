@@ -9,7 +9,9 @@
 //
 // Block (i, j) of N is non-zero iff contacts i and j share a body (Sec. 3.3):
 // the block row of slot s_i lists the contacts incident to i's bodies, merged
-// in contact (= slot) order, each block summing the shared bodies' terms.
+// in slot order (the incidence is sorted by body, then slot), each block
+// summing the shared bodies' terms.  Slots follow the contact order unless
+// persistent slots are kept across time steps.
 #include <cmath>
 
 #include "dense.h"
@@ -20,9 +22,11 @@ namespace {
 
 constexpr int kT = 256;
 
-// incidence entries: key = body, value = (contact << 1) | is_role_A
-__global__ void incidence_kernel(int nc, int M, const int32_t* __restrict__ a,
+// incidence entries: key = (body << sbits) | slot, value = (contact << 1) |
+// is_role_A
+__global__ void incidence_kernel(int nc, int M, int sbits, const int32_t* __restrict__ a,
                                  const int32_t* __restrict__ b,
+                                 const int32_t* __restrict__ slot,
                                  const int32_t* __restrict__ offs,
                                  uint64_t* __restrict__ key, int32_t* __restrict__ val) {
   const int i = blockIdx.x * kT + threadIdx.x;
@@ -30,10 +34,11 @@ __global__ void incidence_kernel(int nc, int M, const int32_t* __restrict__ a,
   const bool wall = b[i] >= M;
   int w = offs[i];
   const int bodyB = wall ? a[i] : b[i];
-  key[w] = (uint64_t)bodyB;
+  const uint64_t sl = (uint64_t)slot[i];
+  key[w] = ((uint64_t)bodyB << sbits) | sl;
   val[w] = i << 1;
   if (!wall) {
-    key[w + 1] = (uint64_t)a[i];
+    key[w + 1] = ((uint64_t)a[i] << sbits) | sl;
     val[w + 1] = (i << 1) | 1;
   }
 }
@@ -44,15 +49,15 @@ __global__ void entries_per_contact_kernel(int nc, int M, const int32_t* __restr
   if (i < nc) cnt[i] = b[i] >= M ? 1 : 2;
 }
 
-__global__ void body_ptr_kernel(int nent, int M, const uint64_t* __restrict__ key,
+__global__ void body_ptr_kernel(int nent, int M, int sbits, const uint64_t* __restrict__ key,
                                 int32_t* __restrict__ ptr) {
   // ptr[body] = first entry of body; ptr[M] = nent (bodies without entries
   // get the start of the next body with entries, filled by a backward pass)
   const int e = blockIdx.x * kT + threadIdx.x;
   if (e >= nent) return;
-  const int bk = (int)key[e];
-  if (e == 0 || (int)key[e - 1] != bk) {
-    const int prev = e == 0 ? -1 : (int)key[e - 1];
+  const int bk = (int)(key[e] >> sbits);
+  if (e == 0 || (int)(key[e - 1] >> sbits) != bk) {
+    const int prev = e == 0 ? -1 : (int)(key[e - 1] >> sbits);
     for (int q = prev + 1; q <= bk; ++q) ptr[q] = e;
   }
   if (e == nent - 1)
@@ -158,9 +163,12 @@ __global__ void fill_rows_kernel(int nslots, int M, double mbar,
   int pB = bptr[B], eB = bptr[B + 1];
   int pA = A >= 0 ? bptr[A] : 0, eA = A >= 0 ? bptr[A + 1] : 0;
   while (pB < eB || pA < eA) {
-    const int jB = pB < eB ? (bent[pB] >> 1) : INT32_MAX;
-    const int jA = pA < eA ? (bent[pA] >> 1) : INT32_MAX;
-    const int j = jB < jA ? jB : jA;
+    const int sB = pB < eB ? slot[bent[pB] >> 1] : INT32_MAX;
+    const int sA = pA < eA ? slot[bent[pA] >> 1] : INT32_MAX;
+    const int sj = sB < sA ? sB : sA;
+    const int j = sB == sj ? (bent[pB] >> 1) : (bent[pA] >> 1);
+    const int jB = sB == sj ? j : -1;
+    const int jA = sA == sj ? j : -1;
     double blk[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     double Dj[6][3];
     if (jB == j) {  // shares body B of contact i
@@ -308,16 +316,18 @@ void assemble_qp(Ctx& c) {
   qp.body_ent.ensure(sizeof(int32_t) * necap);
   qp.body_ptr.ensure(sizeof(int32_t) * (M + 1));
   if (nent > 0) {
-    incidence_kernel<<<div_up(nc, kT), kT, 0, s>>>(nc, M, ct.a.as<int32_t>(),
-                                                  ct.b.as<int32_t>(), c.offs.as<int32_t>(),
-                                                  c.pk.as<uint64_t>(),
+    int sbits = 1;
+    while (((int64_t)1 << sbits) < nslots) ++sbits;
+    incidence_kernel<<<div_up(nc, kT), kT, 0, s>>>(nc, M, sbits, ct.a.as<int32_t>(),
+                                                  ct.b.as<int32_t>(), ct.slot.as<int32_t>(),
+                                                  c.offs.as<int32_t>(), c.pk.as<uint64_t>(),
                                                   qp.body_ent.as<int32_t>());
     QTP_CHECK_LAUNCH();
     int bits = 1;
     while (((int64_t)1 << bits) < M) ++bits;
-    radix_sort_pairs(s, c.pk.as<uint64_t>(), qp.body_ent.as<int32_t>(), nent, bits,
-                     c.sk, c.sv, c.sh, c.ss);
-    body_ptr_kernel<<<div_up(nent, kT), kT, 0, s>>>(nent, M, c.pk.as<uint64_t>(),
+    radix_sort_pairs(s, c.pk.as<uint64_t>(), qp.body_ent.as<int32_t>(), nent,
+                     bits + sbits, c.sk, c.sv, c.sh, c.ss);
+    body_ptr_kernel<<<div_up(nent, kT), kT, 0, s>>>(nent, M, sbits, c.pk.as<uint64_t>(),
                                                    qp.body_ptr.as<int32_t>());
     QTP_CHECK_LAUNCH();
   } else {

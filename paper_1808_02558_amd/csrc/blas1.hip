@@ -166,6 +166,41 @@ __global__ void nonfinite_kernel(const double* __restrict__ x, int64_t n,
 
 // ---- block Jacobi -----------------------------------------------------------
 
+// L^-1 (lower triangle, row-major) of chol(A + shift I) for the symmetric
+// 3x3 A given by its lower triangle; false when a pivot is not positive.
+__device__ bool chol_inv3(double a00, double a10, double a11, double a20, double a21,
+                          double a22, double shift, double out[6]) {
+  a00 += shift;
+  a11 += shift;
+  a22 += shift;
+  if (!(a00 > 0.0)) return false;
+  const double l00 = sqrt(a00);
+  const double l10 = a10 / l00;
+  const double l20 = a20 / l00;
+  const double d1 = a11 - l10 * l10;
+  if (!(d1 > 0.0)) return false;
+  const double l11 = sqrt(d1);
+  const double l21 = (a21 - l20 * l10) / l11;
+  const double d2 = a22 - l20 * l20 - l21 * l21;
+  if (!(d2 > 0.0)) return false;
+  const double l22 = sqrt(d2);
+  const double m00 = 1.0 / l00;
+  const double m11 = 1.0 / l11;
+  const double m22 = 1.0 / l22;
+  const double m10 = -l10 * m00 / l11;
+  const double m21 = -l21 * m11 / l22;
+  const double m20 = -(l20 * m00 + l21 * m10) / l22;
+  out[0] = m00; out[1] = m10; out[2] = m11;
+  out[3] = m20; out[4] = m21; out[5] = m22;
+  return isfinite(m00) && isfinite(m10) && isfinite(m11) && isfinite(m20) &&
+         isfinite(m21) && isfinite(m22);
+}
+
+// Block-Jacobi factors.  A diagonal block of S is positive definite, but late
+// in the PDIP a barrier term lambda/(-f) g g^T can exceed the rest by 1e16
+// and rounding then breaks the Cholesky; the preconditioner only needs an
+// SPD approximation, so the block is shifted by 1e-14, 1e-12, ... times its
+// largest diagonal entry until the factorisation succeeds.
 __global__ void bj_factor_kernel(int nslots, const int32_t* __restrict__ rp,
                                  const int32_t* __restrict__ col,
                                  const double* __restrict__ val,
@@ -180,37 +215,15 @@ __global__ void bj_factor_kernel(int nslots, const int32_t* __restrict__ rp,
     bad[0] = 1;
   } else {
     const double* A = val + (int64_t)b * 9;
-    // Cholesky A = L L^T of the symmetric part (lower triangle read)
     const double a00 = A[0], a10 = A[3], a11 = A[4], a20 = A[6], a21 = A[7],
                  a22 = A[8];
-    if (!(a00 > 0.0)) {
+    const double dmax = fmax(fabs(a00), fmax(fabs(a11), fabs(a22)));
+    bool ok = chol_inv3(a00, a10, a11, a20, a21, a22, 0.0, out);
+    for (double rel = 1e-14; !ok && rel <= 1e-6; rel *= 100.0)
+      ok = chol_inv3(a00, a10, a11, a20, a21, a22, rel * dmax, out);
+    if (!ok) {
       bad[0] = 1;
-    } else {
-      const double l00 = sqrt(a00);
-      const double l10 = a10 / l00;
-      const double l20 = a20 / l00;
-      const double d1 = a11 - l10 * l10;
-      if (!(d1 > 0.0)) {
-        bad[0] = 1;
-      } else {
-        const double l11 = sqrt(d1);
-        const double l21 = (a21 - l20 * l10) / l11;
-        const double d2 = a22 - l20 * l20 - l21 * l21;
-        if (!(d2 > 0.0)) {
-          bad[0] = 1;
-        } else {
-          const double l22 = sqrt(d2);
-          // inverse of the lower-triangular L
-          const double m00 = 1.0 / l00;
-          const double m11 = 1.0 / l11;
-          const double m22 = 1.0 / l22;
-          const double m10 = -l10 * m00 / l11;
-          const double m21 = -l21 * m11 / l22;
-          const double m20 = -(l20 * m00 + l21 * m10) / l22;
-          out[0] = m00; out[1] = m10; out[2] = m11;
-          out[3] = m20; out[4] = m21; out[5] = m22;
-        }
-      }
+      for (int q = 0; q < 6; ++q) out[q] = (q == 0 || q == 2 || q == 5) ? 1.0 : 0.0;
     }
   }
   for (int q = 0; q < 6; ++q) Linv[(int64_t)s * 6 + q] = out[q];

@@ -16,6 +16,8 @@
 //  * t1 = normalise(n x e_k), k = argmin |n_k| (lowest k on ties), t2 = n x t1;
 //  * key: 21-bit-per-axis Morton code of the key point over the bounding box
 //    of the spheres, x most significant; order by (key, a, b).
+#include <algorithm>
+#include <climits>
 #include <cmath>
 
 #include "dense.h"
@@ -277,6 +279,223 @@ __global__ void frames_kernel(int nc, int M, int nslots,
   slot[i] = (int32_t)(((int64_t)i * nslots) / nc);
 }
 
+// ---- slot re-use across time steps (Sec. 3.3) --------------------------------
+
+__global__ void pair_keys_kernel(int nc, const int32_t* __restrict__ a,
+                                 const int32_t* __restrict__ b, uint64_t* __restrict__ out) {
+  const int i = blockIdx.x * kT + threadIdx.x;
+  if (i < nc) out[i] = ((uint64_t)(uint32_t)a[i] << 32) | (uint32_t)b[i];
+}
+
+// old[i] = slot of the same pair in the previous step or -1; marks taken
+// slots and flags the new contacts
+__global__ void lookup_kernel(int nc, const int32_t* __restrict__ a,
+                              const int32_t* __restrict__ b,
+                              const uint64_t* __restrict__ prev,
+                              const int32_t* __restrict__ prev_slot, int np,
+                              int32_t* __restrict__ old, int* __restrict__ taken,
+                              int* __restrict__ isnew) {
+  const int i = blockIdx.x * kT + threadIdx.x;
+  if (i >= nc) return;
+  const uint64_t key = ((uint64_t)(uint32_t)a[i] << 32) | (uint32_t)b[i];
+  int lo = 0, hi = np;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (prev[mid] < key) lo = mid + 1; else hi = mid;
+  }
+  if (lo < np && prev[lo] == key) {
+    const int s = prev_slot[lo];
+    old[i] = s;
+    taken[s] = 1;
+    isnew[i] = 0;
+  } else {
+    old[i] = -1;
+    isnew[i] = 1;
+  }
+}
+
+// taken -> free flags in place (entry nslots is the scan's terminator)
+__global__ void flip_kernel(int nslots, int* __restrict__ f) {
+  const int s = blockIdx.x * kT + threadIdx.x;
+  if (s < nslots) f[s] = 1 - f[s];
+  else if (s == nslots) f[s] = 0;
+}
+
+__global__ void free_list_kernel(int nslots, const int* __restrict__ flag,
+                                 const int* __restrict__ pos, int32_t* __restrict__ list) {
+  const int s = blockIdx.x * kT + threadIdx.x;
+  if (s < nslots && flag[s]) list[pos[s]] = s;
+}
+
+// val[k] = (index in the free list of the first free slot at or after the
+// fresh slot of the k-th new contact) - k
+__global__ void new_val_kernel(int nc, int nslots, const int32_t* __restrict__ old,
+                               const int* __restrict__ rank,
+                               const int32_t* __restrict__ list, int nfree,
+                               int* __restrict__ val) {
+  const int i = blockIdx.x * kT + threadIdx.x;
+  if (i >= nc || old[i] >= 0) return;
+  const int64_t tau = ((int64_t)i * nslots) / nc;
+  int lo = 0, hi = nfree;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (list[mid] < tau) lo = mid + 1; else hi = mid;
+  }
+  val[rank[i]] = lo - rank[i];
+}
+
+// inclusive max-scan in blocks of kScanItems; block maxima to bmax
+constexpr int kScanItems = 4 * kT;
+__global__ void max_scan_block_kernel(int n, int* __restrict__ v, int* __restrict__ bmax) {
+  __shared__ int sh[kT];
+  const int base = blockIdx.x * kScanItems + threadIdx.x * 4;
+  int loc[4];
+  int run = INT_MIN;
+  for (int q = 0; q < 4; ++q) {
+    const int e = base + q;
+    run = max(run, e < n ? v[e] : INT_MIN);
+    loc[q] = run;
+  }
+  sh[threadIdx.x] = run;
+  __syncthreads();
+  for (int o = 1; o < kT; o <<= 1) {
+    const int t = threadIdx.x >= o ? sh[threadIdx.x - o] : INT_MIN;
+    __syncthreads();
+    sh[threadIdx.x] = max(sh[threadIdx.x], t);
+    __syncthreads();
+  }
+  const int before = threadIdx.x > 0 ? sh[threadIdx.x - 1] : INT_MIN;
+  for (int q = 0; q < 4; ++q) {
+    const int e = base + q;
+    if (e < n) v[e] = max(loc[q], before);
+  }
+  if (threadIdx.x == kT - 1) bmax[blockIdx.x] = sh[kT - 1];
+}
+
+// exclusive max over the block maxima, in order (one thread: few blocks)
+__global__ void max_scan_carry_kernel(int nb, int* __restrict__ bmax) {
+  if (threadIdx.x != 0) return;
+  int run = INT_MIN;
+  for (int k = 0; k < nb; ++k) {
+    const int t = bmax[k];
+    bmax[k] = run;
+    run = max(run, t);
+  }
+}
+
+__global__ void max_scan_add_kernel(int n, int* __restrict__ v, const int* __restrict__ carry) {
+  const int e = blockIdx.x * kT + threadIdx.x;
+  if (e < n) v[e] = max(v[e], carry[e / kScanItems]);
+}
+
+__global__ void assign_kernel(int nc, const int32_t* __restrict__ old,
+                              const int* __restrict__ rank, const int* __restrict__ mx,
+                              const int32_t* __restrict__ list, int nfree,
+                              int32_t* __restrict__ slot, int* __restrict__ overflow) {
+  const int i = blockIdx.x * kT + threadIdx.x;
+  if (i >= nc) return;
+  if (old[i] >= 0) {
+    slot[i] = old[i];
+    return;
+  }
+  const int k = rank[i];
+  const int64_t j = (int64_t)k + mx[k];
+  if (j >= nfree) overflow[0] = 1;  // benign race: every writer stores 1
+  else slot[i] = list[j];
+}
+
+// Persistent slots from the previous step's map; leaves ct.slot (the fresh
+// map) untouched when a new contact finds no free slot.
+void persistent_slots(Ctx& c, int nc, int nslots) {
+  Contacts& ct = c.ct;
+  const hipStream_t s = c.stream;
+  ct.old_slot.ensure(sizeof(int32_t) * nc);
+  ct.taken.ensure(sizeof(int) * (nslots + 1));
+  ct.free_pos.ensure(sizeof(int) * (nslots + 1));
+  ct.free_list.ensure(sizeof(int32_t) * std::max(nslots, 1));
+  ct.new_rank.ensure(sizeof(int) * (nc + 1));
+  ct.new_val.ensure(sizeof(int) * (nc + 1));
+  c.cnt.ensure(sizeof(int) * (nc + 1));
+  QTP_HIP(hipMemsetAsync(ct.taken.get(), 0, sizeof(int) * (nslots + 1), s));
+  QTP_HIP(hipMemsetAsync(c.cnt.as<int>() + nc, 0, sizeof(int), s));
+  lookup_kernel<<<div_up(nc, kT), kT, 0, s>>>(
+      nc, ct.a.as<int32_t>(), ct.b.as<int32_t>(), ct.prev_pair.as<uint64_t>(),
+      ct.prev_slot.as<int32_t>(), ct.prev_n, ct.old_slot.as<int32_t>(),
+      ct.taken.as<int>(), c.cnt.as<int>());
+  QTP_CHECK_LAUNCH();
+  flip_kernel<<<div_up(nslots + 1, kT), kT, 0, s>>>(nslots, ct.taken.as<int>());
+  QTP_CHECK_LAUNCH();
+  exclusive_scan(s, ct.taken.as<int>(), ct.free_pos.as<int>(), nslots + 1, c.ss);
+  exclusive_scan(s, c.cnt.as<int>(), ct.new_rank.as<int>(), nc + 1, c.ss);
+  int hv[2] = {0, 0};
+  QTP_HIP(hipMemcpyAsync(&hv[0], ct.free_pos.as<int>() + nslots, sizeof(int),
+                         hipMemcpyDeviceToHost, s));
+  QTP_HIP(hipMemcpyAsync(&hv[1], ct.new_rank.as<int>() + nc, sizeof(int),
+                         hipMemcpyDeviceToHost, s));
+  QTP_HIP(hipStreamSynchronize(s));
+  const int nfree = hv[0], K = hv[1];
+  free_list_kernel<<<div_up(nslots, kT), kT, 0, s>>>(
+      nslots, ct.taken.as<int>(), ct.free_pos.as<int>(), ct.free_list.as<int32_t>());
+  QTP_CHECK_LAUNCH();
+  if (K > 0) {
+    new_val_kernel<<<div_up(nc, kT), kT, 0, s>>>(
+        nc, nslots, ct.old_slot.as<int32_t>(), ct.new_rank.as<int>(),
+        ct.free_list.as<int32_t>(), nfree, ct.new_val.as<int>());
+    QTP_CHECK_LAUNCH();
+    const int nb = div_up(K, kScanItems);
+    ct.scan_tmp.ensure(sizeof(int) * nb);
+    max_scan_block_kernel<<<nb, kT, 0, s>>>(K, ct.new_val.as<int>(), ct.scan_tmp.as<int>());
+    QTP_CHECK_LAUNCH();
+    if (nb > 1) {
+      max_scan_carry_kernel<<<1, 64, 0, s>>>(nb, ct.scan_tmp.as<int>());
+      QTP_CHECK_LAUNCH();
+      max_scan_add_kernel<<<div_up(K, kT), kT, 0, s>>>(K, ct.new_val.as<int>(),
+                                                      ct.scan_tmp.as<int>());
+      QTP_CHECK_LAUNCH();
+    }
+  }
+  int* ovf = c.flag.as<int>() + 1;
+  QTP_HIP(hipMemsetAsync(ovf, 0, sizeof(int), s));
+  // the assignment goes to new_rank's storage only after it is read: use the
+  // free-position buffer (nslots + 1 >= nc ints) as the output
+  int32_t* out = reinterpret_cast<int32_t*>(ct.free_pos.get());
+  assign_kernel<<<div_up(nc, kT), kT, 0, s>>>(
+      nc, ct.old_slot.as<int32_t>(), ct.new_rank.as<int>(), ct.new_val.as<int>(),
+      ct.free_list.as<int32_t>(), nfree, out, ovf);
+  QTP_CHECK_LAUNCH();
+  int hovf = 0;
+  QTP_HIP(hipMemcpyAsync(&hovf, ovf, sizeof(int), hipMemcpyDeviceToHost, s));
+  QTP_HIP(hipStreamSynchronize(s));
+  if (hovf) {
+    ct.rebuilt = true;
+    ct.n_persistent = 0;
+    return;
+  }
+  QTP_HIP(hipMemcpyAsync(ct.slot.get(), out, sizeof(int32_t) * nc,
+                         hipMemcpyDeviceToDevice, s));
+  ct.n_persistent = nc - K;
+}
+
+// The pairs of this step sorted, with their slots, for the next step.
+void save_slot_map(Ctx& c, int nc, int nslots, int key_bits) {
+  Contacts& ct = c.ct;
+  const hipStream_t s = c.stream;
+  ct.prev_pair.ensure(sizeof(uint64_t) * std::max(nc, 1));
+  ct.prev_slot.ensure(sizeof(int32_t) * std::max(nc, 1));
+  if (nc > 0) {
+    pair_keys_kernel<<<div_up(nc, kT), kT, 0, s>>>(nc, ct.a.as<int32_t>(),
+                                                  ct.b.as<int32_t>(),
+                                                  ct.prev_pair.as<uint64_t>());
+    QTP_CHECK_LAUNCH();
+    QTP_HIP(hipMemcpyAsync(ct.prev_slot.get(), ct.slot.get(), sizeof(int32_t) * nc,
+                           hipMemcpyDeviceToDevice, s));
+    radix_sort_pairs(s, ct.prev_pair.as<uint64_t>(), ct.prev_slot.as<int32_t>(), nc,
+                     key_bits, c.sk, c.sv, c.sh, c.ss);
+  }
+  ct.prev_n = nc;
+  ct.prev_nslots = nslots;
+}
+
 }  // namespace
 
 int detect_contacts(Ctx& c) {
@@ -444,6 +663,16 @@ int detect_contacts(Ctx& c) {
     QTP_HIP(hipMemcpyAsync(&bad, c.flag.get(), sizeof(int), hipMemcpyDeviceToHost, s));
     QTP_HIP(hipStreamSynchronize(s));
     QTP_REQUIRE(bad == 0, QTP_E_NUMERIC, "coincident sphere centres");
+  }
+  ct.rebuilt = false;
+  ct.n_persistent = 0;
+  if (c.cfg.slot_mode == 1) {
+    if (nc > 0 && ct.prev_n > 0 && ct.prev_nslots == nslots) persistent_slots(c, nc, nslots);
+    int bbits = 1;
+    while (((int64_t)1 << bbits) < (int64_t)M + sc.nw) ++bbits;
+    save_slot_map(c, nc, nslots, 32 + bbits);
+  } else {
+    ct.prev_n = -1;
   }
   QTP_HIP(hipStreamSynchronize(s));
   ct.valid = true;

@@ -52,6 +52,14 @@ struct Contacts {
   bool valid = false;
   DevBuf a, b, key, phi, frame, slot, bounds;
   DevBuf cell_key, cell_idx, cell_start, cell_stop;
+  // slot re-use across time steps: the previous step's pairs (a << 32 | b,
+  // sorted) with their slots, and per current contact its old slot or -1
+  DevBuf prev_pair, prev_slot, old_slot;
+  DevBuf taken, free_pos, free_list, new_rank, new_val, scan_tmp;
+  int prev_n = -1;           // contacts of the previous step (-1: none)
+  int prev_nslots = 0;
+  int n_persistent = 0;      // contacts of this step that kept their slot
+  bool rebuilt = false;      // this step fell back to the fresh map
 };
 
 // The QP of Sec. 2.3 in scaled units on the slot layout: N (BSR3, with
@@ -73,6 +81,9 @@ struct Pdip {
   DevBuf part;                         // reduction partials
   bool have_gamma = false;
   std::vector<qtp_newton_record> log; // one record per Newton step
+  DevBuf gamma_prev;                   // last converged solution (slot layout)
+  bool have_prev = false;
+  int64_t prev_n = 0;
 };
 
 // Optional event timing of selected kernels on the context's stream.

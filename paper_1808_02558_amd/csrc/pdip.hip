@@ -89,6 +89,38 @@ __global__ void init_kernel(int nc, double mu, const int32_t* __restrict__ slot,
   lam[nc + i] = 1.0 / (-cs.f2);
 }
 
+// start from the previous step's impulses for contacts that kept their slot
+// (normal part at least floor_n, friction pulled inside 0.9 of the cone),
+// the cold start for the others; multipliers on the central path of t0
+__global__ void prev_start_kernel(int nc, double mu, double t0, double floor_n,
+                                  const int32_t* __restrict__ slot,
+                                  const int32_t* __restrict__ old_slot,
+                                  const double* __restrict__ gprev,
+                                  double* __restrict__ gamma, double* __restrict__ lam) {
+  const int i = blockIdx.x * kT + threadIdx.x;
+  if (i >= nc) return;
+  const int64_t u = 3 * (int64_t)slot[i];
+  double gn = 1.0, g1 = 0.0, g2 = 0.0, tc = 1.0;
+  if (old_slot[i] >= 0) {
+    gn = fmax(gprev[u], floor_n);
+    g1 = gprev[u + 1];
+    g2 = gprev[u + 2];
+    const double gt = sqrt(g1 * g1 + g2 * g2), cap = 0.9 * mu * gn;
+    if (gt > cap) {
+      g1 *= cap / gt;
+      g2 *= cap / gt;
+    }
+    tc = t0;
+  }
+  gamma[u] = gn;
+  gamma[u + 1] = g1;
+  gamma[u + 2] = g2;
+  ContactState cs;
+  eval(mu, gn, g1, g2, 0.0, 0.0, cs);
+  lam[i] = 1.0 / (tc * (-cs.f1));
+  lam[nc + i] = 1.0 / (tc * (-cs.f2));
+}
+
 // partial: -f^T lambda
 __global__ void gap_kernel(int nc, double mu, const int32_t* __restrict__ slot,
                            const double* __restrict__ gamma,
@@ -265,7 +297,8 @@ double now_ms() {
 
 }  // namespace
 
-static int pdip_run(Ctx& c, qtp_step_stats* st, bool warm) {
+// start: 0 cold (Sec. 3.3), 1 previous step's impulses, 2 learned
+static int pdip_run(Ctx& c, qtp_step_stats* st, int start) {
   QTP_REQUIRE(c.qp.valid && !c.qp.stale, QTP_E_STATE, "assemble before the PDIP solve");
   const hipStream_t s = c.stream;
   Scene& sc = c.scene;
@@ -340,8 +373,13 @@ static int pdip_run(Ctx& c, qtp_step_stats* st, bool warm) {
     st->ms_pdip = 0.0;
     return QTP_OK;
   }
-  if (warm) {
+  if (start == 2) {
     mlp_warm_start(c, c.cfg.warm_t0, gamma, lam);
+  } else if (start == 1) {
+    prev_start_kernel<<<div_up(nc, kT), kT, 0, s>>>(
+        nc, mu, c.cfg.warm_t0, c.cfg.warm_floor, slot, c.ct.old_slot.as<int32_t>(),
+        pd.gamma_prev.as<double>(), gamma, lam);
+    QTP_CHECK_LAUNCH();
   } else {
     init_kernel<<<div_up(nc, kT), kT, 0, s>>>(nc, mu, slot, gamma, lam);
     QTP_CHECK_LAUNCH();
@@ -355,7 +393,8 @@ static int pdip_run(Ctx& c, qtp_step_stats* st, bool warm) {
     QTP_CHECK_LAUNCH();
     gap = 0.0;
     for (double v : read_part(c, nb)) gap += v;
-    const double t = mu_pd * m / gap;
+    // mu m / eta, capped at the t whose central point meets the gap tolerance
+    const double t = std::min(mu_pd * m / gap, mu_pd / c.cfg.pdip_gap_tol);
     // u = N gamma + r
     bsr_spmv(s, c.nslots, n, qp.rp.as<int32_t>(), qp.col.as<int32_t>(),
              qp.valN.as<double>(), gamma, u);
@@ -523,28 +562,49 @@ int pdip_solve(Ctx& c, qtp_step_stats* st) {
   st->warm_started = 0;
   st->warm_fallback = 0;
   st->warm_iterations = 0;
-  if (c.cfg.warm_start == 2 && c.mlp.have_params && c.ct.nc > 0) {
-    st->warm_started = 1;
-    int rc = QTP_NOT_CONVERGED;
+  st->persistent_contacts = c.ct.n_persistent;
+  st->slots_rebuilt = c.ct.rebuilt ? 1 : 0;
+  Pdip& pd = c.pd;
+  int start = 0;
+  if (c.cfg.warm_start == 2 && c.mlp.have_params && c.ct.nc > 0) start = 2;
+  if (c.cfg.warm_start == 1 && pd.have_prev && c.ct.n_persistent > 0 &&
+      pd.prev_n == (int64_t)1 << c.scene.log2n)
+    start = 1;
+  int rc = QTP_NOT_CONVERGED;
+  if (start != 0) {
+    st->warm_started = start;
     try {
-      rc = pdip_run(c, st, true);
+      rc = pdip_run(c, st, start);
     } catch (const Error& e) {
       if (e.status != QTP_E_NUMERIC) throw;
     }
-    if (rc == QTP_OK) return rc;
-    const int wit = st->pdip_iterations;
-    const double wpre = st->ms_precond, wsol = st->ms_solve, wpd = st->ms_pdip;
-    const int wfg = st->fgmres_iterations;
-    rc = pdip_run(c, st, false);
-    st->warm_fallback = 1;
-    st->warm_iterations = wit;
-    st->ms_precond += wpre;
-    st->ms_solve += wsol;
-    st->ms_pdip += wpd;  // the failed warm run is part of the cost
-    st->fgmres_iterations += wfg;
-    return rc;
+    if (rc != QTP_OK) {
+      const int wit = st->pdip_iterations;
+      const double wpre = st->ms_precond, wsol = st->ms_solve, wpd = st->ms_pdip;
+      const int wfg = st->fgmres_iterations;
+      rc = pdip_run(c, st, 0);
+      st->warm_fallback = 1;
+      st->warm_iterations = wit;
+      st->ms_precond += wpre;
+      st->ms_solve += wsol;
+      st->ms_pdip += wpd;  // the failed warm run is part of the cost
+      st->fgmres_iterations += wfg;
+    }
+  } else {
+    rc = pdip_run(c, st, 0);
   }
-  return pdip_run(c, st, false);
+  // keep the solution on the slot layout for a start from it next step
+  if (rc == QTP_OK && c.ct.nc > 0) {
+    const int64_t n = (int64_t)1 << c.scene.log2n;
+    pd.gamma_prev.ensure(sizeof(double) * n);
+    QTP_HIP(hipMemcpyAsync(pd.gamma_prev.get(), pd.gamma.get(), sizeof(double) * n,
+                           hipMemcpyDeviceToDevice, c.stream));
+    pd.have_prev = true;
+    pd.prev_n = n;
+  } else {
+    pd.have_prev = false;
+  }
+  return rc;
 }
 
 void gather_impulses(Ctx& c, double* out) {

@@ -137,3 +137,77 @@ def test_closed_forms_through_the_abi(torch, theta, mu):
     else:
         en = (math.cos(theta) + mu * math.sin(theta)) / (1 + 3.5 * mu * mu)
         assert abs(gn - en) < 1e-6 and abs(gt - mu * en) < 1e-6
+
+
+@pytest.mark.parametrize("name,shift", [("lattice_box", 0.3), ("loose_box", 0.3),
+                                        ("lattice_box", None)])
+def test_persistent_slots_match_oracle(torch, name, shift):
+    """Two configurations in a row with slot re-use: the second step's slots
+    (kept, filled forward, or rebuilt) and its assembled matrix match the
+    oracle bit for bit / to rounding."""
+    import dataclasses
+    sc = scene(name)
+    rng = np.random.default_rng(17)
+    if shift is None:  # equal radii: permuting the positions renames the bodies
+        x2 = sc.x[rng.permutation(sc.M)]
+    else:
+        x2 = sc.x + rng.uniform(-shift, shift, sc.x.shape) * sc.delta
+    sc2 = dataclasses.replace(sc, x=np.ascontiguousarray(x2))
+    d = sc.log2n
+    c1 = contacts.detect(sc)
+    s1, _ = contacts.slot_map(c1.nc, d)
+    c2 = contacts.detect(sc2)
+    s2, pers, rebuilt = contacts.slot_map_persistent(c1.a, c1.b, s1, c2.a, c2.b, d)
+    ctx = make_ctx(torch, sc, slot_mode=1)
+    try:
+        n1 = ctx.qtp_detect()
+        g1 = ctx.qtp_get_contacts(n1)
+        ctx.qtp_set_bodies(dev(torch, sc2.x), dev(torch, sc2.v), dev(torch, sc2.w),
+                           dev(torch, sc2.radius), dev(torch, sc2.mass))
+        n2 = ctx.qtp_detect()
+        g2 = ctx.qtp_get_contacts(n2)
+        ctx.qtp_assemble()
+        rp, col, val, rg = ctx.qtp_get_qp(d)
+    finally:
+        ctx.close()
+    print(f"{name}: {c1.nc} -> {c2.nc} contacts, {int(pers.sum())} kept their slot, "
+          f"rebuilt {rebuilt}")
+    assert np.array_equal(g1["slot"].cpu().numpy(), s1)
+    assert n2 == c2.nc
+    assert np.array_equal(g2["a"].cpu().numpy(), c2.a)
+    assert np.array_equal(g2["slot"].cpu().numpy(), s2)
+    N, r, D = assembly.qp_data(sc2, c2)
+    gbar, vbar = assembly.scales(sc2)
+    Npad = helpers.pad_matrix((N * (gbar / vbar)).tocsr(), s2, d)
+    rp_o, col_o, val_o = helpers.to_bsr3(Npad, d)
+    assert np.array_equal(rp.cpu().numpy(), rp_o)
+    assert np.array_equal(col.cpu().numpy(), col_o)
+    assert np.abs(val.cpu().numpy() - val_o).max() <= 1e-13 * np.abs(val_o).max()
+    rpad = helpers.pad_vector(r / vbar, s2, d)
+    assert np.abs(rg.cpu().numpy() - rpad).max() <= 1e-12 * np.abs(rpad).max()
+
+
+def test_previous_step_start(torch):
+    """Two time steps with slot re-use; the second starts from the first's
+    impulses (warm_start = 1) and reaches the cold start's solution."""
+    sc = cases.small_box()
+    cfg = dict(solve_tol=1e-10, fgmres_maxit=5000, qtt_mode=0, slot_mode=1)
+    out = {}
+    for ws in (0, 1):
+        ctx = make_ctx(torch, sc, warm_start=ws, **cfg)
+        try:
+            ctx.qtp_step()
+            rc, st = ctx.qtp_step()
+            g = ctx.qtp_get_impulses(st.n_contacts).cpu().numpy()
+            x, v, w = (t.cpu().numpy() for t in ctx.qtp_get_state(sc.M))
+        finally:
+            ctx.close()
+        out[ws] = (rc, st, g, v)
+    (rc0, cold, g0, v0), (rc1, warm, g1, v1) = out[0], out[1]
+    print(f"second step: cold {cold.pdip_iterations} PDIP its, previous-step start "
+          f"{warm.pdip_iterations} (fallback {warm.warm_fallback}), "
+          f"{warm.persistent_contacts} of {warm.n_contacts} contacts kept their slot")
+    assert rc0 == 0 and rc1 == 0
+    assert warm.warm_started == 1 and warm.persistent_contacts > 0
+    assert np.linalg.norm(g1 - g0) <= 1e-4 * np.linalg.norm(g0)
+    assert np.abs(v1 - v0).max() <= 1e-6 * np.linalg.norm(sc.gravity) * sc.h

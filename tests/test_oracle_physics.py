@@ -156,3 +156,77 @@ def test_slot_map_hierarchy_example():
     assert list(slot) == [0, 1, 2, 3, 4] and not dummy.any()
     slot, dummy = contacts.slot_map(3, 4)
     assert list(slot) == [0, 1, 3] and list(np.nonzero(dummy)[0]) == [2, 4]
+
+
+def test_persistent_slots_reduce_to_the_fresh_map():
+    """No previous contacts: every contact is new and takes its fresh slot."""
+    a = np.arange(7)
+    b = a + 100
+    slot, pers, rebuilt = contacts.slot_map_persistent([], [], [], a, b, 5)
+    fresh, _ = contacts.slot_map(7, 5)
+    assert not rebuilt and not pers.any()
+    assert np.array_equal(slot, fresh)
+
+
+def test_persistent_slots_keep_the_tree_and_fill_forward():
+    """Hand-worked case on 2^5 (10 slots): contacts (0,1) (2,3) (4,5) sat in
+    slots 0, 3, 6; now (2,3) is gone and two new contacts appear around the
+    persistent ones."""
+    prev_a, prev_b, prev_s = [0, 2, 4], [1, 3, 5], [0, 3, 6]
+    a = np.array([0, 7, 4, 8])
+    b = np.array([1, 9, 5, 10])
+    slot, pers, rebuilt = contacts.slot_map_persistent(prev_a, prev_b, prev_s, a, b, 5)
+    # fresh slots floor(q * 10 / 4) = 0, 2, 5, 7; persistent keep 0 and 6;
+    # (7,9) takes 2; (8,10) takes the first free slot >= max(7, 3) = 7
+    assert not rebuilt
+    assert pers.tolist() == [True, False, True, False]
+    assert slot.tolist() == [0, 2, 6, 7]
+
+
+def test_persistent_slots_rebuild_when_no_slot_is_left():
+    """The last new contact finds no free slot after its fresh one: rebuild."""
+    prev_a, prev_b, prev_s = [0], [1], [9]
+    a = np.array([2, 0])
+    b = np.array([3, 1])
+    # 2^5 -> 10 slots; new (2,3) has fresh slot 0, persistent (0,1) keeps 9
+    slot, pers, rebuilt = contacts.slot_map_persistent(prev_a, prev_b, prev_s, a, b, 5)
+    assert not rebuilt and slot.tolist() == [0, 9]
+    # many new contacts behind a persistent one in the last slot
+    a = np.array([0] + list(range(2, 11)))
+    b = np.array([1] + list(range(102, 111)))
+    slot, pers, rebuilt = contacts.slot_map_persistent(prev_a, prev_b, prev_s, a, b, 5)
+    fresh, _ = contacts.slot_map(10, 5)
+    assert rebuilt and np.array_equal(slot, fresh) and not pers.any()
+
+
+def test_persistent_slots_brute_force_properties():
+    """Random small cases: the map is injective, persistent contacts keep
+    their slots, and new contacts are increasing and at or after their fresh
+    slots."""
+    rng = np.random.default_rng(11)
+    for trial in range(200):
+        d = int(rng.integers(4, 8))
+        S = (1 << d) // 3
+        n0 = int(rng.integers(0, S + 1))
+        pool = rng.permutation(3 * S)[: 2 * S]
+        prev = pool[:n0]
+        prev_slot = np.sort(rng.permutation(S)[:n0])
+        keep = prev[rng.random(n0) < 0.7]
+        new = pool[n0: n0 + int(rng.integers(0, S - len(keep) + 1))]
+        cur = rng.permutation(np.concatenate([keep, new]))[:S]
+        a, b = cur // 1000, cur % 1000 + 1000
+        pa, pb = prev // 1000, prev % 1000 + 1000
+        slot, pers, rebuilt = contacts.slot_map_persistent(pa, pb, prev_slot, a, b, d)
+        assert len(set(slot.tolist())) == len(slot)
+        if rebuilt:
+            continue
+        old = {(int(x), int(y)): int(s) for x, y, s in zip(pa, pb, prev_slot)}
+        fresh, _ = contacts.slot_map(len(cur), d)
+        last = -1
+        for q in range(len(cur)):
+            key = (int(a[q]), int(b[q]))
+            if key in old:
+                assert pers[q] and slot[q] == old[key]
+            else:
+                assert not pers[q] and slot[q] >= fresh[q] and slot[q] > last
+                last = slot[q]
