@@ -4,6 +4,9 @@ One step is one frictional-contact time step of the whole hot path on the
 GPU: contact detection and ordering, assembly of N and r, the PDIP loop
 (per Newton iteration: barrier blocks, block-Jacobi factors, the QTT inverse
 where the preconditioner mode uses it, FGMRES to 1e-8), and integration.
+By default the steps re-use information across time steps as Sec. 3.3 does:
+persistent contacts keep their slots and start the PDIP from their previous
+normal impulse; the untimed warm-up step starts cold.
 Workload: the seeded rectangular hopper fill of 131,072 spheres (radius
 uniform in [0.8, 1.2] cm, mu = 0.4, h = 1e-3 s), ~3.4e5 contacts padded to
 2^20 unknowns.
@@ -275,10 +278,14 @@ def main():
     ap.add_argument("--qtt-mode", type=int, default=2, choices=[0, 1, 2],
                     help="0 block-Jacobi only, 1 QTT inverse always, 2 per-step trial")
     ap.add_argument("--scene", default="hopper")
-    ap.add_argument("--slot-mode", type=int, default=0, choices=[0, 1],
+    ap.add_argument("--slot-mode", type=int, default=1, choices=[0, 1],
                     help="1: contacts keep their slots across time steps")
-    ap.add_argument("--warm-start", type=int, default=0, choices=[0, 1],
-                    help="1: start each PDIP from the previous step's impulses")
+    ap.add_argument("--warm-start", type=int, default=1, choices=[0, 1, 3],
+                    help="1: previous step's normal impulses of persistent contacts; "
+                         "3: their whole previous impulses")
+    ap.add_argument("--warm-t0", type=float, default=1.0)
+    ap.add_argument("--warm-floor", type=float, default=0.0)
+    ap.add_argument("--warm-maxit", type=int, default=40)
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -312,7 +319,9 @@ def main():
                 ns_iters=a.ns_iters, ns_iters_hot=a.ns_iters_hot)
     ctx = make_context(binding, torch, sc,
                        **dict(base, precision=a.precision, qtt_mode=a.qtt_mode,
-                              slot_mode=a.slot_mode, warm_start=a.warm_start))
+                              slot_mode=a.slot_mode, warm_start=a.warm_start,
+                              warm_t0=a.warm_t0, warm_floor=a.warm_floor,
+                              warm_maxit=a.warm_maxit))
     n = 1 << sc.log2n
 
     stats, recs = [], []
@@ -381,7 +390,8 @@ def main():
                         f"mu {sc.mu}, h {sc.h}",
             "qtt_mode": a.qtt_mode, "qtt_cores": a.precision, "qtt_eps": a.eps,
             "qtt_rmax": a.rmax, "qtt_rmax_s": a.rmax_s, "slot_mode": a.slot_mode,
-            "warm_start": a.warm_start,
+            "warm_start": a.warm_start, "warm_t0": a.warm_t0,
+            "warm_floor": a.warm_floor, "warm_maxit": a.warm_maxit,
             "fgmres": f"FGMRES({a.restart}) to 1e-8", "pdip_gap_tol": 1e-8,
         },
         "newton_solve_ms": float(np.median(sms)),

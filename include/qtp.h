@@ -76,15 +76,22 @@ typedef struct {
   double pdip_gap_tol;  /* PDIP stop: gap / m */
   double pdip_dual_tol; /* PDIP stop: |r_dual|_inf in scaled units */
   int pdip_maxit;
-  int warm_start;       /* 0 cold; 1 previous step's impulses for contacts that
-                           kept their slot (slot_mode 1), cold for new ones;
-                           2 learned (MLP); 1 and 2 fall back to cold */
+  int warm_start;       /* 0 cold (gamma = (1, 0, 0));
+                           1 Sec. 3.3 re-use: contacts that kept their slot
+                             (slot_mode 1) start from their previous normal
+                             impulse with zero friction, new ones cold;
+                           2 learned (MLP);
+                           3 as 1, keeping the previous friction impulse too;
+                           1-3 fall back to cold after warm_maxit iterations */
   uint64_t seed;
   double warm_t0;       /* central-path parameter of the learned start */
   int qtt_mode;         /* PDIP preconditioner: 0 block-Jacobi only (X = I),
                            1 QTT inverse on every Newton step,
                            2 auto: the first Newton step of a time step is
-                             solved with both, the faster is kept */
+                             solved with both, the faster is kept; after a
+                             lost trial the next 2^k - 1 time steps (k
+                             consecutive losses, k <= 6) skip the trial and
+                             use block-Jacobi */
   double warm_floor;    /* learned and previous-step starts: lower bound on
                            the starting normal impulse in scaled units (keeps
                            the start away from the cone's boundary) */
@@ -93,6 +100,8 @@ typedef struct {
                              slot, new ones take the next free slot at or
                              after their fresh one, rebuilt when none is left
                              (Sec. 3.3, re-use across time steps) */
+  int warm_maxit;       /* PDIP iterations allowed to a warm start before the
+                           cold start takes over */
 } qtp_config;
 
 /* Fills a config with the defaults: FP64, eps 1e-2, rmax 32, rmax_s 16,

@@ -49,6 +49,7 @@ class Config(ctypes.Structure):
         ("qtt_mode", ctypes.c_int),
         ("warm_floor", ctypes.c_double),
         ("slot_mode", ctypes.c_int),
+        ("warm_maxit", ctypes.c_int),
     ]
 
 

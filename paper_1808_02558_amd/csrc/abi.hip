@@ -80,10 +80,11 @@ void qtp::Ctx::check_cfg() {
   QTP_REQUIRE(cfg.solve_mode == 0 || cfg.solve_mode == 1, QTP_E_ARG, "bad solve_mode");
   QTP_REQUIRE(cfg.ns_iters >= 0 && cfg.ns_iters_hot >= 0, QTP_E_ARG, "ns_iters < 0");
   QTP_REQUIRE(cfg.qtt_mode >= 0 && cfg.qtt_mode <= 2, QTP_E_ARG, "qtt_mode out of [0,2]");
-  QTP_REQUIRE(cfg.warm_start >= 0 && cfg.warm_start <= 2, QTP_E_ARG,
-              "warm_start must be 0, 1 or 2");
+  QTP_REQUIRE(cfg.warm_start >= 0 && cfg.warm_start <= 3, QTP_E_ARG,
+              "warm_start must be 0, 1, 2 or 3");
   QTP_REQUIRE(cfg.slot_mode == 0 || cfg.slot_mode == 1, QTP_E_ARG,
               "slot_mode must be 0 or 1");
+  QTP_REQUIRE(cfg.warm_maxit >= 1, QTP_E_ARG, "warm_maxit must be >= 1");
   QTP_REQUIRE(cfg.warm_floor >= 0.0 && std::isfinite(cfg.warm_floor), QTP_E_ARG,
               "warm_floor must be finite and >= 0");
 }
@@ -111,6 +112,7 @@ void qtp_config_default(qtp_config* cfg) {
   cfg->warm_t0 = 100.0;
   cfg->warm_floor = 0.0;
   cfg->slot_mode = 0;
+  cfg->warm_maxit = 100;
   cfg->qtt_mode = 2;
 }
 

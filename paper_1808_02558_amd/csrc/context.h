@@ -147,6 +147,8 @@ struct Ctx {
   bool have_inverse = false;
   bool use_qtt = true;          // apply X (else the block-Jacobi part only)
   bool auto_qtt = false;        // auto mode's choice for the current time step
+  int auto_losses = 0;          // consecutive trials the QTT inverse lost
+  int auto_skip = 0;            // time steps left before the next trial
   Pattern pat;
   int ns_done = 0;              // Newton-Schulz iterations of the last build
   double probe_residual = 0.0;  // rms of z - S~ X z over the probes

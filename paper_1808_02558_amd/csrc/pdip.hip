@@ -89,11 +89,14 @@ __global__ void init_kernel(int nc, double mu, const int32_t* __restrict__ slot,
   lam[nc + i] = 1.0 / (-cs.f2);
 }
 
-// start from the previous step's impulses for contacts that kept their slot
-// (normal part at least floor_n, friction pulled inside 0.9 of the cone),
-// the cold start for the others; multipliers on the central path of t0
+// Start from the previous step (Sec. 3.3, re-using information across time
+// steps): a contact that kept its slot starts from its previous normal
+// impulse (at least floor_n) and, with keep_t, its previous friction impulse
+// pulled inside 0.9 of the cone (the paper zeroes it); other contacts take
+// the cold start.  Multipliers on the central path of t0 for the re-used
+// contacts, of t = 1 for the others.
 __global__ void prev_start_kernel(int nc, double mu, double t0, double floor_n,
-                                  const int32_t* __restrict__ slot,
+                                  int keep_t, const int32_t* __restrict__ slot,
                                   const int32_t* __restrict__ old_slot,
                                   const double* __restrict__ gprev,
                                   double* __restrict__ gamma, double* __restrict__ lam) {
@@ -103,12 +106,14 @@ __global__ void prev_start_kernel(int nc, double mu, double t0, double floor_n,
   double gn = 1.0, g1 = 0.0, g2 = 0.0, tc = 1.0;
   if (old_slot[i] >= 0) {
     gn = fmax(gprev[u], floor_n);
-    g1 = gprev[u + 1];
-    g2 = gprev[u + 2];
-    const double gt = sqrt(g1 * g1 + g2 * g2), cap = 0.9 * mu * gn;
-    if (gt > cap) {
-      g1 *= cap / gt;
-      g2 *= cap / gt;
+    if (keep_t) {
+      g1 = gprev[u + 1];
+      g2 = gprev[u + 2];
+      const double gt = sqrt(g1 * g1 + g2 * g2), cap = 0.9 * mu * gn;
+      if (gt > cap) {
+        g1 *= cap / gt;
+        g2 *= cap / gt;
+      }
     }
     tc = t0;
   }
@@ -377,8 +382,8 @@ static int pdip_run(Ctx& c, qtp_step_stats* st, int start) {
     mlp_warm_start(c, c.cfg.warm_t0, gamma, lam);
   } else if (start == 1) {
     prev_start_kernel<<<div_up(nc, kT), kT, 0, s>>>(
-        nc, mu, c.cfg.warm_t0, c.cfg.warm_floor, slot, c.ct.old_slot.as<int32_t>(),
-        pd.gamma_prev.as<double>(), gamma, lam);
+        nc, mu, c.cfg.warm_t0, c.cfg.warm_floor, c.cfg.warm_start == 3 ? 1 : 0, slot,
+        c.ct.old_slot.as<int32_t>(), pd.gamma_prev.as<double>(), gamma, lam);
     QTP_CHECK_LAUNCH();
   } else {
     init_kernel<<<div_up(nc, kT), kT, 0, s>>>(nc, mu, slot, gamma, lam);
@@ -419,7 +424,9 @@ static int pdip_run(Ctx& c, qtp_step_stats* st, int start) {
       rc = QTP_OK;
       break;
     }
-    if (it >= c.cfg.pdip_maxit) break;
+    if (it >= (start != 0 ? std::min(c.cfg.warm_maxit, c.cfg.pdip_maxit)
+                          : c.cfg.pdip_maxit))
+      break;
     // Newton system
     newton_setup_kernel<<<div_up(nc, kT), kT, 0, s>>>(
         nc, mu, t, slot, qp.diagpos.as<int32_t>(), gamma, lam, u,
@@ -434,7 +441,9 @@ static int pdip_run(Ctx& c, qtp_step_stats* st, int start) {
     qtp_solve_stats ss{};
     int src;
     double sms;
-    if (mode == 2 && it == 0) {
+    const bool trial = mode == 2 && it == 0 && c.auto_skip == 0;
+    if (mode == 2 && it == 0 && !trial) --c.auto_skip;
+    if (trial) {
       // auto: solve the first Newton step with X = I and with the QTT inverse,
       // keep the faster for the rest of the time step
       c.use_qtt = false;
@@ -458,6 +467,14 @@ static int pdip_run(Ctx& c, qtp_step_stats* st, int start) {
       st->fgmres_iterations += ss.iterations + s2.iterations;
       c.auto_qtt = src2 == QTP_OK && ms_b + ms_x < ms_i;
       c.use_qtt = c.auto_qtt;
+      // a lost trial is repeated after 1, 3, 7, ... skipped time steps (at
+      // most 63), a won one at the next step
+      if (c.auto_qtt) {
+        c.auto_losses = 0;
+      } else {
+        c.auto_losses = std::min(c.auto_losses + 1, 6);
+        c.auto_skip = (1 << c.auto_losses) - 1;
+      }
       if (c.auto_qtt) {
         QTP_HIP(hipMemcpyAsync(dgamma, pd.dtrial.get(), sizeof(double) * n,
                                hipMemcpyDeviceToDevice, s));
@@ -567,7 +584,8 @@ int pdip_solve(Ctx& c, qtp_step_stats* st) {
   Pdip& pd = c.pd;
   int start = 0;
   if (c.cfg.warm_start == 2 && c.mlp.have_params && c.ct.nc > 0) start = 2;
-  if (c.cfg.warm_start == 1 && pd.have_prev && c.ct.n_persistent > 0 &&
+  if ((c.cfg.warm_start == 1 || c.cfg.warm_start == 3) && pd.have_prev &&
+      c.ct.n_persistent > 0 &&
       pd.prev_n == (int64_t)1 << c.scene.log2n)
     start = 1;
   int rc = QTP_NOT_CONVERGED;
