@@ -88,10 +88,12 @@ typedef struct {
   int qtt_mode;         /* PDIP preconditioner: 0 block-Jacobi only (X = I),
                            1 QTT inverse on every Newton step,
                            2 auto: the first Newton step of a time step is
-                             solved with both, the faster is kept; after a
-                             lost trial the next 2^k - 1 time steps (k
-                             consecutive losses, k <= 6) skip the trial and
-                             use block-Jacobi */
+                             solved with both, the faster is kept (the QTT
+                             solve stops at twice the block-Jacobi
+                             iterations plus 10, a loss); after a lost trial
+                             the next 2^k - 1 time steps (k consecutive
+                             losses, k <= 6) skip the trial and use
+                             block-Jacobi */
   double warm_floor;    /* learned and previous-step starts: lower bound on
                            the starting normal impulse in scaled units (keeps
                            the start away from the cone's boundary) */

@@ -460,7 +460,18 @@ static int pdip_run(Ctx& c, qtp_step_stats* st, int start) {
       pd.dtrial.ensure(sizeof(double) * n);
       qtp_solve_stats s2{};
       t0 = now_ms();
-      const int src2 = newton_solve(c, pd.rhs.as<double>(), pd.dtrial.as<double>(), &s2);
+      // the QTT trial may use twice the block-Jacobi trial's iterations (plus
+      // 10): beyond that it has lost, so stop paying for it
+      int src2;
+      {
+        struct Restore {
+          int& v;
+          int old;
+          ~Restore() { v = old; }
+        } restore{c.cfg.fgmres_maxit, c.cfg.fgmres_maxit};
+        c.cfg.fgmres_maxit = std::min(c.cfg.fgmres_maxit, 2 * ss.iterations + 10);
+        src2 = newton_solve(c, pd.rhs.as<double>(), pd.dtrial.as<double>(), &s2);
+      }
       const double ms_x = now_ms() - t0;
       st->qtt_trial_iterations = s2.iterations;
       st->ms_solve += ms_i + ms_x;

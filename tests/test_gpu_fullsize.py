@@ -160,3 +160,45 @@ def test_pdip_time_step_at_full_size(torch, hopper):
     scale = np.abs(Dg).max()
     assert np.abs(dv - Dg[:, :3]).max() <= 1e-9 * scale
     assert np.abs(dw - Dg[:, 3:]).max() <= 1e-9 * scale
+
+
+def test_reused_time_step_at_full_size(torch, hopper):
+    """Two time steps with the bench's re-use settings (persistent slots,
+    previous normal impulses): the second step converges, most contacts keep
+    their slots, and its impulses satisfy the KKT conditions of the QP the
+    library assembled for that step."""
+    sc = hopper["sc"]
+    d = sc.log2n
+    ctx = make_ctx(torch, sc, solve_mode=1, solve_tol=1e-8, fgmres_restart=30,
+                   fgmres_maxit=3000, qtt_mode=2, slot_mode=1, warm_start=1,
+                   warm_t0=1.0, warm_maxit=40)
+    try:
+        rc0, st0 = ctx.qtp_step()
+        nc = ctx.qtp_detect()
+        ctx.qtp_assemble()
+        rp, col, val, rg = ctx.qtp_get_qp(d)
+        slot = ctx.qtp_get_contacts(nc)["slot"].cpu().numpy()
+        rc, st = ctx.qtp_pdip_solve()
+        g = ctx.qtp_get_impulses(nc).cpu().numpy()
+        gbar = sc.mass.mean() * np.linalg.norm(sc.gravity) * sc.h
+    finally:
+        ctx.close()
+    print(f"second step: {st.pdip_iterations} PDIP its (first {st0.pdip_iterations}), "
+          f"start {st.warm_started}, fallback {st.warm_fallback}, "
+          f"{st.persistent_contacts} of {nc} slots kept")
+    assert rc == 0 and st.converged and st.warm_started == 1
+    assert st.persistent_contacts >= 0.9 * nc
+    n = 1 << d
+    S = n // 3
+    A = sp.bsr_matrix((val.cpu().numpy().reshape(-1, 3, 3), col.cpu().numpy(),
+                       rp.cpu().numpy()), shape=(3 * S, 3 * S)).tocsr()
+    gpad = np.zeros(n)
+    idx = helpers.unknown_index(slot)
+    gpad[idx] = (g / gbar).reshape(-1)
+    u = (A @ gpad[:3 * S] + rg.cpu().numpy()[:3 * S])
+    u = u[idx].reshape(-1, 3)
+    gs = (g / gbar).reshape(-1, 3)
+    mu = sc.mu
+    assert np.all(np.hypot(gs[:, 1], gs[:, 2]) <= mu * gs[:, 0] * (1 + 1e-12))
+    assert np.all(u[:, 0] - mu * np.hypot(u[:, 1], u[:, 2]) >= -1e-3)
+    assert np.all(np.abs((gs * u).sum(1)) <= 1e-3 + st.gap * 2 * nc)
