@@ -266,7 +266,7 @@ def mlp_form(binding, torch, sc, base, train_steps=2, epochs=12, batch=4096, lr=
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="f32", choices=["f64", "f32", "bf16"])
     ap.add_argument("--rmax", type=int, default=32)

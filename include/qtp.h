@@ -82,7 +82,9 @@ typedef struct {
                              impulse with zero friction, new ones cold;
                            2 learned (MLP);
                            3 as 1, keeping the previous friction impulse too;
-                           1-3 fall back to cold after warm_maxit iterations */
+                           1-3 fall back to cold after warm_maxit iterations;
+                           after k consecutive fallbacks the next 2^k - 1
+                           solves (k <= 6) start cold */
   uint64_t seed;
   double warm_t0;       /* central-path parameter of the learned start */
   int qtt_mode;         /* PDIP preconditioner: 0 block-Jacobi only (X = I),
@@ -115,7 +117,8 @@ void qtp_config_default(qtp_config* cfg);
 qtp_status qtp_create(const qtp_config* cfg, void* hip_stream, qtp_ctx* out);
 void qtp_destroy(qtp_ctx ctx);
 const char* qtp_last_error(qtp_ctx ctx);
-/* Updates the configuration of an existing context (host struct). */
+/* Updates the configuration of an existing context (host struct); the auto
+ * mode's trial and the warm-start back-offs restart from zero. */
 qtp_status qtp_set_config(qtp_ctx ctx, const qtp_config* cfg);
 
 /* ---------------------------------------------------------------------------

@@ -169,6 +169,9 @@ qtp_status qtp_set_config(qtp_ctx ctx, const qtp_config* cfg) {
       throw;
     }
     c.X.lp_prec = 0;  // reduced-precision copies follow the new precision
+    // a new configuration starts the trial and warm-start back-offs afresh
+    c.auto_losses = c.auto_skip = 0;
+    c.pd.warm_losses = c.pd.warm_skip = 0;
     return QTP_OK;
   });
 }

@@ -15,7 +15,7 @@
 //          one-workgroup pass after it sums them, forms the Hessenberg column
 //          h_j = h1 + h2 with h_{j+1,j}^2 = |w|^2 - |h2|^2 (the norm of
 //          w - V h2 by Pythagoras, V being orthonormal), applies the Givens
-//          rotations and writes the residual estimate |g_{j+1}| to a
+//          rotations and stores the residual estimate |g_{j+1}| into a
 //          host-visible status ring.
 // Every reduction is deterministic: per-block partials in a fixed layout and
 // a fixed-order sum in the second pass; no floating-point atomics.  (A
@@ -177,7 +177,7 @@ __global__ __launch_bounds__(kThreads) void orth_kernel(
 // rotation and the residual estimate (one thread).
 __global__ __launch_bounds__(kFinThreads) void orth_finish_kernel(
     int nblk, int nvec, const double* __restrict__ partial, double* __restrict__ d,
-    ArnStatus* __restrict__ status, int64_t tag) {
+    double* __restrict__ status, int64_t tag) {
   __shared__ double fin[kArnMaxRestart + 1];
   __shared__ double H[kArnMaxRestart + 1], cs[kArnMaxRestart], sn[kArnMaxRestart];
   const int j = nvec - 1;
@@ -217,10 +217,11 @@ __global__ __launch_bounds__(kFinThreads) void orth_finish_kernel(
   const double gj = g[j];
   g[j + 1] = -s * gj;
   g[j] = c * gj;
-  ArnStatus* st = status + (tag & (kArnRing - 1));
-  st->res = fabs(s * gj);
-  st->hn = hn;
-  __hip_atomic_store(&st->tag, tag, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  // one word, so no ordering against other stores is needed: a breakdown
+  // (hn = 0) ends the cycle like convergence does
+  const double res = hn == 0.0 ? 0.0 : fabs(s * gj);
+  __hip_atomic_store(status + (tag & (kArnRing - 1)), res, __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // y = H(0:jend, 0:jend)^-1 g(0:jend) by back substitution (H staged in LDS).

@@ -83,6 +83,8 @@ struct Pdip {
   std::vector<qtp_newton_record> log; // one record per Newton step
   DevBuf gamma_prev;                   // last converged solution (slot layout)
   bool have_prev = false;
+  int warm_losses = 0;                 // consecutive failed warm starts
+  int warm_skip = 0;                   // steps left that start cold
   int64_t prev_n = 0;
 };
 

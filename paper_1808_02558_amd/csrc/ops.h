@@ -67,17 +67,15 @@ enum : int {
   kArnH = 448,     // Hessenberg, column j at kArnH + j * kArnLd
   kArnDoubles = kArnH + kArnLd * kArnMaxRestart
 };
-// One residual estimate, written by the device into pinned host memory.
-struct ArnStatus {
-  double res;   // |g_{j+1}|: the least-squares residual after step j
-  double hn;    // h_{j+1,j}
-  double pad;
-  int64_t tag;  // written last; identifies the step
-};
+// The host-visible status ring holds one double per Arnoldi step: the
+// least-squares residual |g_{j+1}| (0 on a breakdown, NaN when the step went
+// non-finite), written by the device with a single system-scope store into a
+// slot the host has set to -1 (empty).
+constexpr double kArnEmpty = -1.0;
 struct Arnoldi {
   double* d = nullptr;          // kArnDoubles doubles (device)
   double* partial = nullptr;    // arnoldi_partial_doubles(n) doubles (device)
-  ArnStatus* status = nullptr;  // kArnRing entries, device view of pinned memory
+  double* status = nullptr;     // kArnRing entries, device view of pinned memory
 };
 size_t arnoldi_partial_doubles(int64_t n);
 // V_j = (src - sum_{l<nprev} h2_l V_l) * inv, inv = d[kArnInv] when nprev > 0
@@ -90,7 +88,7 @@ void arnoldi_next(hipStream_t s, const Arnoldi& a, int nprev, const double* V,
 void arnoldi_dots(hipStream_t s, const Arnoldi& a, int nvec, const double* V,
                   int64_t n, const double* w);
 // w -= V h1; h2 = V^T w; Hessenberg column nvec - 1, Givens rotation and the
-// status entry `tag`.
+// status entry tag mod kArnRing.
 void arnoldi_orth(hipStream_t s, const Arnoldi& a, int nvec, const double* V,
                   int64_t n, double* w, int64_t tag);
 // d[kArnY..] = least-squares solution of the first jend columns

@@ -599,6 +599,12 @@ int pdip_solve(Ctx& c, qtp_step_stats* st) {
       c.ct.n_persistent > 0 &&
       pd.prev_n == (int64_t)1 << c.scene.log2n)
     start = 1;
+  // after k consecutive failed warm starts the next 2^k - 1 steps start cold
+  // (k <= 6): a start that has stopped helping is not paid for every step
+  if (start != 0 && pd.warm_skip > 0) {
+    --pd.warm_skip;
+    start = 0;
+  }
   int rc = QTP_NOT_CONVERGED;
   if (start != 0) {
     st->warm_started = start;
@@ -607,7 +613,11 @@ int pdip_solve(Ctx& c, qtp_step_stats* st) {
     } catch (const Error& e) {
       if (e.status != QTP_E_NUMERIC) throw;
     }
-    if (rc != QTP_OK) {
+    if (rc == QTP_OK) {
+      pd.warm_losses = 0;
+    } else {
+      pd.warm_losses = std::min(pd.warm_losses + 1, 6);
+      pd.warm_skip = (1 << pd.warm_losses) - 1;
       const int wit = st->pdip_iterations;
       const double wpre = st->ms_precond, wsol = st->ms_solve, wpd = st->ms_pdip;
       const int wfg = st->fgmres_iterations;

@@ -89,42 +89,41 @@ double residual(Ctx& c, const double* rhs, const double* x, double* r) {
 
 Arnoldi arnoldi_state(Ctx& c) {
   if (c.arn_status.empty()) {
-    c.arn_status.alloc(sizeof(ArnStatus) * kArnRing);
-    ArnStatus* h = c.arn_status.host<ArnStatus>();
-    for (int i = 0; i < kArnRing; ++i) h[i] = ArnStatus{0.0, 0.0, 0.0, -1};
+    c.arn_status.alloc(sizeof(double) * kArnRing);
+    double* h = c.arn_status.host<double>();
+    for (int i = 0; i < kArnRing; ++i) h[i] = kArnEmpty;
   }
   c.arn_d.ensure(sizeof(double) * kArnDoubles);
   c.arn_partial.ensure(sizeof(double) * arnoldi_partial_doubles(c.n));
   Arnoldi a;
   a.d = c.arn_d.as<double>();
   a.partial = c.arn_partial.as<double>();
-  a.status = c.arn_status.dev<ArnStatus>();
+  a.status = c.arn_status.dev<double>();
   return a;
 }
 
-// Waits until the device has written status entry `tag`.  Polls the stream
-// now and then so that a failed or finished stream cannot leave the host
-// spinning.
-ArnStatus wait_status(Ctx& c, int64_t tag) {
-  volatile ArnStatus* e = c.arn_status.host<ArnStatus>() + (tag & (kArnRing - 1));
+// Waits until the device has stored status entry `tag`, returns it and empties
+// the slot again (the device is at most one step ahead, far less than the
+// ring).  Polls the stream now and then so that a failed or finished stream
+// cannot leave the host spinning.
+double wait_status(Ctx& c, int64_t tag) {
+  double* e = c.arn_status.host<double>() + (tag & (kArnRing - 1));
   int64_t spins = 0;
-  while (__atomic_load_n(&e->tag, __ATOMIC_ACQUIRE) != tag) {
+  double v;
+  while ((v = *reinterpret_cast<volatile double*>(e)) == kArnEmpty) {
     if ((++spins & 1023) == 0) {
       const hipError_t q = hipStreamQuery(c.stream);
       if (q == hipSuccess) {
-        if (__atomic_load_n(&e->tag, __ATOMIC_ACQUIRE) == tag) break;
+        v = *reinterpret_cast<volatile double*>(e);
+        if (v != kArnEmpty) break;
         throw Error(QTP_E_HIP, "FGMRES: residual estimate missing after the stream drained");
       }
       if (q != hipErrorNotReady) QTP_HIP(q);
     }
     __builtin_ia32_pause();
   }
-  ArnStatus out;
-  out.res = e->res;
-  out.hn = e->hn;
-  out.pad = 0.0;
-  out.tag = tag;
-  return out;
+  *reinterpret_cast<volatile double*>(e) = kArnEmpty;
+  return v;
 }
 
 // Right-preconditioned FGMRES(m).  Within a restart cycle the host queues step
@@ -146,7 +145,11 @@ int fgmres(Ctx& c, const double* rhs, double* x, qtp_solve_stats* st) {
   const bool qtt = c.have_inverse && c.use_qtt;
   const double* Linv = c.Linv.as<double>();
 
-  const double bnorm = norm2(c, rhs);
+  const double bnorm = norm2(c, rhs);  // synchronises: no step is in flight
+  {
+    double* ring = c.arn_status.host<double>();
+    for (int i = 0; i < kArnRing; ++i) ring[i] = kArnEmpty;
+  }
   QTP_HIP(hipMemsetAsync(x, 0, sizeof(double) * n, c.stream));
   if (!(std::isfinite(bnorm))) throw Error(QTP_E_NUMERIC, "rhs is not finite");
   if (bnorm == 0.0) {
@@ -198,19 +201,20 @@ int fgmres(Ctx& c, const double* rhs, double* x, qtp_solve_stats* st) {
         arnoldi_orth(c.stream, a, j + 1, V, n, w, tags[j]);
       }
       if (j >= 1) {
-        const ArnStatus e = wait_status(c, tags[j - 1]);
-        if (!std::isfinite(e.res) || !std::isfinite(e.hn))
-          throw Error(QTP_E_NUMERIC, "FGMRES breakdown (NaN)");
-        if (e.res <= tol * bnorm || e.hn == 0.0) {
+        const double res = wait_status(c, tags[j - 1]);
+        if (!std::isfinite(res)) throw Error(QTP_E_NUMERIC, "FGMRES breakdown (NaN)");
+        if (res <= tol * bnorm) {
+          // converged or broke down; step j is discarded, but its status
+          // slot is emptied once it lands so the ring stays consistent
+          (void)wait_status(c, tags[j]);
           jend = j;
           break;
         }
       }
     }
     if (jend == jmax) {
-      const ArnStatus e = wait_status(c, tags[jmax - 1]);
-      if (!std::isfinite(e.res) || !std::isfinite(e.hn))
-        throw Error(QTP_E_NUMERIC, "FGMRES breakdown (NaN)");
+      const double res = wait_status(c, tags[jmax - 1]);
+      if (!std::isfinite(res)) throw Error(QTP_E_NUMERIC, "FGMRES breakdown (NaN)");
     }
     it += jend;
     arnoldi_solve(c.stream, a, jend);
