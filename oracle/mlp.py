@@ -7,7 +7,7 @@ the optimum but off the central path makes the method take short steps
 (Sec. 3.3, "Re-using information across timesteps").  The learned warm start
 predicts the impulses of each contact from local features and starts the PDIP
 from that prediction, placed strictly inside the cone and on the central path
-of a chosen t0; the cold start stays as the fallback and the judge.
+of a chosen t0; the cold start stays as the fallback and the reference.
 
 Readings (the design is not in the paper)
 -----------------------------------------
