@@ -286,6 +286,7 @@ def main():
     ap.add_argument("--warm-t0", type=float, default=1.0)
     ap.add_argument("--warm-floor", type=float, default=0.0)
     ap.add_argument("--warm-maxit", type=int, default=40)
+    ap.add_argument("--pdip-maxit", type=int, default=100)
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -316,7 +317,8 @@ def main():
     sc = scenes.make_scene(a.scene)
     base = dict(qtt_rmax=a.rmax, qtt_rmax_s=a.rmax_s, qtt_eps=a.eps, solve_mode=1,
                 solve_tol=1e-8, fgmres_restart=a.restart, fgmres_maxit=3000,
-                ns_iters=a.ns_iters, ns_iters_hot=a.ns_iters_hot)
+                ns_iters=a.ns_iters, ns_iters_hot=a.ns_iters_hot,
+                pdip_maxit=a.pdip_maxit)
     ctx = make_context(binding, torch, sc,
                        **dict(base, precision=a.precision, qtt_mode=a.qtt_mode,
                               slot_mode=a.slot_mode, warm_start=a.warm_start,
